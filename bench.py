@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Throughput of the fleet-staging hot path on one MI355X.
+
+One step = the whole hot path over one synthetic instance: the FP64 haversine
+cost table, base ranking, and the Tabu search for its full iteration count.
+The default workload is 500 bases, 1,500 hospitals, 20,000 missions,
+30 vehicles, range 1,000 km, tenure 15, 500 iterations.
+
+The metric is mission x move evaluations per second: every Tabu iteration
+scores K*(B-K) swap moves over M missions.  It is reported for the whole step
+(cost table and ranking included in the time).  Alongside:
+  roofline      the swap sweep's algorithmic bytes per launch over its average
+                launch time (HIP events on its own stream), against 8 TB/s HBM;
+  cpu_baseline  the CPU oracle on a bounded sample of the same search.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3),
+                    help="workload size preset (default: 500 bases x 20,000 missions)")
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="Tabu iterations of the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_traffic.json"),
+                    help="HBM traffic per sweep launch measured with rocprofv3 counters")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the instance-level sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2001_05291_amd import fleetstage as fs
+    from paper_2001_05291_amd import synth
+
+    c = synth.CONFIGS[args.config]
+    B, M, K, R, T, N = c["B"], c["M"], c["K"], c["R"], c["T"], c["N"]
+    log(f"[bench] building instance B={B} H={c['H']} M={M} K={K} R={R} T={T} N={N}")
+    inst = synth.config_instance(args.config)
+    dev = torch.device("cuda:0")
+    bases = torch.from_numpy(inst.bases).to(dev)
+    missions = torch.from_numpy(inst.missions).to(dev)
+    fs.lib()
+
+    result = {}
+
+    def step():
+        C, _ = fs.build_cost_table(bases, missions)
+        r = fs.tabu_solve(C, K, R, T, N, want_assign=True, want_trace=False)
+        result["r"] = r
+        return C
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+
+    fs.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sweep_ms, sweep_n = fs.timing_read("sweep")
+    refresh_ms, refresh_n = fs.timing_read("refresh")
+    fin_ms, fin_n = fs.timing_read("finalize")
+    fs.timing_enable(False)
+    log(f"[bench] timed {args.steps} steps in {elapsed:.4f} s")
+
+    evals_per_step = N * K * (B - K) * M
+    value = evals_per_step * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # dominant kernel: the swap sweep.  Algorithmic bytes per launch: every
+    # closed row once (4 B per element) + the per-mission state (b1, b2, o1).
+    sweep_bytes = (B - K) * M * 4 + 12 * M
+    sweep_avg_s = (sweep_ms / max(sweep_n, 1)) / 1e3
+    achieved = sweep_bytes / sweep_avg_s / 1e9 if sweep_n else None
+    traffic = None
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        if tj.get("workload") == f"config{args.config}":
+            traffic = tj.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "kernel": "k_sweep", "bytes_per_launch": sweep_bytes,
+                "avg_launch_us": sweep_avg_s * 1e6, "launches": sweep_n}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_cpu = args.cpu_iters or {1: 100, 2: 150, 3: 3}[args.config]
+        log(f"[bench] cpu baseline: oracle table + {n_cpu} Tabu iterations")
+        Co, _ = oracle.cost_table(inst.bases, inst.missions, want_cf=False)
+        t1 = time.perf_counter()
+        oracle.tabu(Co, K, R, T, n_cpu)
+        cpu_s = time.perf_counter() - t1
+        cpu = {"value": n_cpu * K * (B - K) * M / cpu_s, "unit": "MM-evals/s",
+               "cores": oracle.get_threads(), "kind": "oracle",
+               "sample": f"first {n_cpu} of {N} Tabu iterations of the same instance "
+                         f"(oracle cost table, not timed); {cpu_s:.2f} s"}
+        log(f"[bench] cpu baseline {cpu['value']:.3e} MM-evals/s on {cpu['cores']} threads")
+
+    r = result["r"]
+    line = {
+        "metric": "mission x move evals/s",
+        "value": value,
+        "unit": "MM-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"config{args.config}: tabu swap search, B={B} bases, "
+                               f"M={M} missions, K={K} vehicles, R={R} m, T={T}, N={N}",
+                   "B": B, "H": c["H"], "M": M, "K": K, "R": R, "T": T, "N": N,
+                   "seed": c["seed"], "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"sweep_ms_per_launch": sweep_ms / max(sweep_n, 1),
+                   "refresh_ms_per_launch": refresh_ms / max(refresh_n, 1),
+                   "finalize_ms_per_launch": fin_ms / max(fin_n, 1),
+                   "best_coverage": r.coverage, "best_distance_m": r.distance,
+                   "best_iter": r.best_iter},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

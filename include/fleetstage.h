@@ -1,0 +1,183 @@
+/*
+ * fleetstage.h -- C ABI of libfleetstage.so, the MI355X (gfx950) compute path for
+ * fleet staging of air ambulances:
+ *   J. Tassone, G. Pond, S. Choudhury, "Algorithms for Optimizing Fleet Staging
+ *   of Air Ambulances", arXiv:2001.05291.
+ *
+ * The problem (Section 3): K vehicles are placed on K distinct bases out of B
+ * candidates.  A mission m is a round trip base -> pickup -> delivery -> the
+ * same base; its cost from base b is C[b][m] (int32 metres).  A placement S
+ * serves every mission from its nearest open base (the objective of Eq. 2 read
+ * as nearest-base assignment); a mission is covered when that cost is within
+ * the range R.  Placements are ranked by coverage (more is better), then by
+ * the total distance of covered missions (less is better).  The search is the
+ * base ranking of Section 4.1 (Algorithm 1) followed by the Tabu search of
+ * Section 4.3 (Algorithm 3) over swap moves (i open, j closed).
+ *
+ * Conventions for every call:
+ *  - Ids are 0-based int32.  Bulk arrays are DEVICE pointers owned by the
+ *    caller; small structs (fs_params, fs_score, fs_instance) are HOST pointers.
+ *  - The cost table is row-major, one row per base, with a row pitch ldc
+ *    (elements, ldc >= M); all B*ldc elements must be readable, the columns
+ *    [M, ldc) are ignored.  Entries must lie in [0, INT32_MAX); INT32_MAX is
+ *    reserved as "no base".  Values outside that range give unspecified
+ *    search results but never an out-of-bounds access (costs never index
+ *    memory).  Rows are read with 16-byte vector loads when ldc % 4 == 0 and C
+ *    is 16-byte aligned, otherwise with 4-byte loads.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    stream-ordered.  Calls that return host-side results synchronise the
+ *    stream before returning; the others return after enqueueing.
+ *  - On a negative status nothing was written to outputs that the call had not
+ *    validated first; fs_last_error() returns a message for the calling thread.
+ *  - The library keeps no caller pointer after a call returns.
+ *  - Scratch memory is allocated by the library per call, stream-ordered
+ *    (hipMallocAsync/hipFreeAsync on the caller's stream).
+ */
+#ifndef FLEETSTAGE_H
+#define FLEETSTAGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fs_status;
+#define FS_OK 0
+#define FS_PENDING 1          /* serve: result not ready yet */
+#define FS_E_INVALID (-1)     /* argument validation failed */
+#define FS_E_NOMEM (-2)       /* device or host allocation failed */
+#define FS_E_DEVICE (-3)      /* a HIP runtime call failed */
+#define FS_E_BUDGET (-4)      /* serve: request can never fit the HBM budget */
+#define FS_E_NOTFOUND (-5)    /* serve: unknown instance or ticket */
+#define FS_E_CLOSED (-6)      /* serve: server closed */
+#define FS_E_INTERNAL (-7)    /* a device-side consistency check failed */
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *fs_last_error(void);
+/* Library version string. */
+const char *fs_version(void);
+
+/* Search parameters.
+ *  tenure     T >= 0: both bases of an executed move stay tabu for the next T
+ *             iterations (Algorithm 3's TabuList / TabuCounter).
+ *  iterations N >= 0: Tabu runs exactly N iterations; local search at most N.
+ *  range_m    R in [0, INT32_MAX): a mission is covered when its nearest open
+ *             base costs at most R metres.
+ *  mode       0 = Tabu search (Algorithm 3, best admissible move with
+ *             aspiration); 1 = local search baseline (Algorithm 2 read as
+ *             steepest descent: strictly improving moves only, stop at a local
+ *             optimum). */
+typedef struct {
+    int32_t tenure;
+    int32_t iterations;
+    int32_t range_m;
+    int32_t mode;
+} fs_params;
+
+/* Best placement found: coverage and distance of covered missions, and the
+ * iteration (1-based; 0 = the initial placement) at which it was reached. */
+typedef struct {
+    int32_t coverage;
+    int32_t best_iter;
+    int64_t distance;
+} fs_score;
+
+/* One iteration of the search (40 bytes).  out_base/in_base are -1 and moved
+ * is 0 when no move was admissible.  cur_* is the current placement's value
+ * after the iteration, best_* the best value so far. */
+typedef struct {
+    int32_t iter;
+    int32_t out_base;
+    int32_t in_base;
+    int32_t moved;
+    int32_t cur_cov;
+    int32_t best_cov;
+    int64_t cur_dist;
+    int64_t best_dist;
+} fs_trace_rec;
+
+/* Cost table (Eq. 1; Algorithm 1, the Distances fill; Section 3 mission legs).
+ *   Cf[b][m] = (hav(b, p_m) + hav(p_m, d_m)) + hav(d_m, b)   (legs = 3)
+ *   Cf[b][m] =  hav(b, p_m) + hav(d_m, b)                     (legs = 2)
+ *   C[b][m]  = Cf[b][m] rounded half to even to int32 metres,
+ * with hav the haversine great-circle distance of Eq. 1 on a sphere of radius
+ * earth_radius_m (0 selects 6,371,000 m), computed in FP64.
+ *   base_latlon_deg  device, B x 2 doubles (lat, lon in degrees)
+ *   mission_pd_deg   device, M x 4 doubles (pickup lat, lon, delivery lat, lon)
+ *   C                device, B rows of pitch ldc (>= M) int32, written [0, M)
+ *   Cf               device, same shape as C in doubles, or NULL
+ * Errors: FS_E_INVALID for B < 1, M < 1, ldc < M, legs not 2 or 3, NULL
+ * required pointer, negative radius; FS_E_INVALID also if a cost would not fit
+ * int32 (radius > 1.1e8 m).  Enqueues and returns. */
+fs_status fs_build_cost_table(const double *base_latlon_deg, int32_t B,
+                              const double *mission_pd_deg, int32_t M,
+                              double earth_radius_m, int32_t legs,
+                              int32_t *C, int64_t ldc, double *Cf, void *stream);
+
+/* Base ranking (Section 4.1, Algorithm 1's Top_Vals): row sums
+ * S_b = sum_m C[b][m] (int64), and the K bases of smallest (S_b, b).
+ *   open_out  device, K int32, the chosen ids in ascending id order
+ *   order_out device, K int32, the chosen ids by rank (smallest sum first), or NULL
+ *   row_sums  device, B int64, or NULL
+ * Errors: FS_E_INVALID for B < 1, M < 1, K < 1, K > B, ldc < M, NULL C or
+ * open_out.  Enqueues and returns. */
+fs_status fs_rank_bases(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K,
+                        int32_t *open_out, int32_t *order_out, int64_t *row_sums,
+                        void *stream);
+
+/* Scores of every swap move of placement `open` (the checks of Algorithms 2
+ * and 3): for slot k (base i = open[k]) and closed base j, the value of the
+ * placement open - i + j.
+ *   open     device, K distinct base ids (slot order is the row order of the output)
+ *   cov_out  device, K x B int32; entry [k*B + j] for closed j, -1 for open j
+ *   dist_out device, K x B int64; same layout
+ * Errors: FS_E_INVALID for bad sizes, R out of range, K > 1024,
+ * repeated or out-of-range ids in `open` (checked on the host after a copy).
+ * Synchronises the stream (it reads `open` on the host). */
+fs_status fs_move_scores(const int32_t *C, int64_t ldc, int32_t B, int32_t M,
+                         const int32_t *open, int32_t K, int32_t range_m,
+                         int32_t *cov_out, int64_t *dist_out, void *stream);
+
+/* Tabu search (Section 4.3, Algorithm 3) from the base-ranking placement
+ * (Algorithm 1) or from init_open, for exactly p->iterations iterations.
+ * Per iteration t: every swap (i open, j closed) is scored; a move is
+ * admissible when tabu_until[i] < t and tabu_until[j] < t, or when its score
+ * is strictly better than the best so far (aspiration); the best admissible
+ * move by (coverage desc, distance asc, i asc, j asc) is executed, or none
+ * when no move is admissible; then tabu_until[i] = tabu_until[j] = t + T and
+ * the best placement is replaced on strict improvement.  p->mode = 1 runs the
+ * local-search baseline instead.
+ *   init_open     device, K distinct ids, or NULL (base ranking)
+ *   best_open_out device, K int32, best placement in ascending id order
+ *   score_out     host, the best placement's value
+ *   assign_out    device, M int32: nearest open base of the best placement
+ *                 (lowest id among equal costs), -1 when beyond R; or NULL
+ *   trace_out     device, p->iterations records, or NULL
+ * Errors: FS_E_INVALID for bad sizes or parameters (T < 0, N < 0, R out of
+ * range, mode not 0/1, K > 1024, bad init ids); FS_E_INTERNAL if the
+ * refreshed value of the placement disagrees with the executed move's score.
+ * Synchronises the stream before returning. */
+fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K,
+                        const fs_params *p, const int32_t *init_open,
+                        int32_t *best_open_out, fs_score *score_out,
+                        int32_t *assign_out, fs_trace_rec *trace_out, void *stream);
+
+/* Diagnostics: device time of the search kernels, for roofline reporting.
+ * While enabled (on != 0), every launch of a kernel group is bracketed by a
+ * pair of HIP events recorded on the stream it is launched on; groups are
+ * "sweep" (move evaluation, including the chunk-merge kernel when the mission
+ * axis is split), "refresh" (per-mission open-base state) and "finalize"
+ * (argmax and move application).  Enabling or disabling discards what was
+ * recorded.  Process-wide; not meant for concurrent solves. */
+fs_status fs_timing_enable(int32_t on);
+/* Waits for the recorded events of `group`, returns their summed elapsed time
+ * (milliseconds) and number of launches, and clears them.  FS_E_INVALID for an
+ * unknown group name. */
+fs_status fs_timing_read(const char *group, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLEETSTAGE_H */

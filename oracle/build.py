@@ -13,7 +13,7 @@ OUT = os.path.join(_HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+    cmd = ["gcc", "-std=c11", "-O3", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
            "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

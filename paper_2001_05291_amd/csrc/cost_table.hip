@@ -1,0 +1,126 @@
+// Cost table: FP64 haversine round trips rounded to int32 metres.
+//
+// Eq. 1 (Section 3) gives the haversine great-circle distance; Section 3
+// defines a mission as pickup, delivery and return to the same base, and
+// Algorithm 1 (Section 4.1) fills the base-by-mission Distances table.  A
+// workgroup covers 256 missions of kBasesPerBlock base rows: the per-mission
+// terms (angles in radians, cosines, the pickup->delivery leg) are computed
+// once by a prologue kernel, so the main kernel evaluates two haversines per
+// (base, mission) entry.  The kernel is bound by FP64 VALU work (two sines,
+// one square root and one arcsine per haversine), not by the int32 writes.
+//
+// This file is compiled with -ffp-contract=off so that every product and sum
+// is rounded separately, in the order written.
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr double kDeg2Rad = 3.14159265358979323846 / 180.0;
+constexpr int kBasesPerBlock = 4;
+
+struct MissionPrep {
+    double *phi_p, *psi_p, *cos_p;
+    double *phi_d, *psi_d, *cos_d;
+    double *pd;  // pickup -> delivery leg
+};
+
+// Haversine of Eq. 1 between point a and point b, angles in radians, with the
+// cosines of the latitudes precomputed.  The radicand is clamped to [0, 1].
+__device__ __forceinline__ double haversine(double phi_a, double psi_a, double cos_a,
+                                            double phi_b, double psi_b, double cos_b,
+                                            double two_r)
+{
+    double s_phi = sin((phi_a - phi_b) / 2.0);
+    double s_psi = sin((psi_a - psi_b) / 2.0);
+    double h = s_phi * s_phi + cos_a * cos_b * (s_psi * s_psi);
+    h = fmin(fmax(h, 0.0), 1.0);
+    return two_r * asin(sqrt(h));
+}
+
+__global__ __launch_bounds__(kBlock) void k_mission_prep(const double *__restrict__ mpd, int32_t M,
+                                                         double two_r, MissionPrep mp)
+{
+    int32_t m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= M) return;
+    const double *q = mpd + 4 * (int64_t)m;
+    double phi_p = q[0] * kDeg2Rad, psi_p = q[1] * kDeg2Rad;
+    double phi_d = q[2] * kDeg2Rad, psi_d = q[3] * kDeg2Rad;
+    double cos_p = cos(phi_p), cos_d = cos(phi_d);
+    mp.phi_p[m] = phi_p;
+    mp.psi_p[m] = psi_p;
+    mp.cos_p[m] = cos_p;
+    mp.phi_d[m] = phi_d;
+    mp.psi_d[m] = psi_d;
+    mp.cos_d[m] = cos_d;
+    mp.pd[m] = haversine(phi_p, psi_p, cos_p, phi_d, psi_d, cos_d, two_r);
+}
+
+// grid: x = mission blocks of kBlock, y = base groups of kBasesPerBlock.
+__global__ __launch_bounds__(kBlock) void k_cost_table(const double *__restrict__ bases, int32_t B,
+                                                       int32_t M, double two_r, int32_t legs,
+                                                       MissionPrep mp, int32_t *__restrict__ C,
+                                                       double *__restrict__ Cf, int64_t ldc)
+{
+    int32_t m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= M) return;
+    double phi_p = mp.phi_p[m], psi_p = mp.psi_p[m], cos_p = mp.cos_p[m];
+    double phi_d = mp.phi_d[m], psi_d = mp.psi_d[m], cos_d = mp.cos_d[m];
+    double pd = mp.pd[m];
+    for (int32_t b0 = blockIdx.y * kBasesPerBlock; b0 < B; b0 += gridDim.y * kBasesPerBlock)
+#pragma unroll
+    for (int q = 0; q < kBasesPerBlock; ++q) {
+        int32_t b = b0 + q;
+        if (b >= B) break;
+        double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
+        double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
+        double cos_b = cos(phi_b);
+        double bp = haversine(phi_b, psi_b, cos_b, phi_p, psi_p, cos_p, two_r);
+        double db = haversine(phi_d, psi_d, cos_d, phi_b, psi_b, cos_b, two_r);
+        double v = (legs == 3) ? (bp + pd) + db : bp + db;
+        int64_t at = (int64_t)b * ldc + m;
+        C[at] = (int32_t)rint(v);
+        if (Cf) Cf[at] = v;
+    }
+}
+
+}  // namespace
+}  // namespace fs
+
+extern "C" fs_status fs_build_cost_table(const double *base_latlon_deg, int32_t B,
+                                         const double *mission_pd_deg, int32_t M,
+                                         double earth_radius_m, int32_t legs, int32_t *C,
+                                         int64_t ldc, double *Cf, void *stream)
+{
+    using namespace fs;
+    if (!base_latlon_deg || !mission_pd_deg || !C)
+        return fail(FS_E_INVALID, "NULL coordinate or output pointer");
+    if (B < 1 || M < 1) return fail(FS_E_INVALID, "B=%d, M=%d: both must be >= 1", B, M);
+    if (ldc < M) return fail(FS_E_INVALID, "row pitch ldc=%lld < M=%d", (long long)ldc, M);
+    if (legs != 2 && legs != 3) return fail(FS_E_INVALID, "legs=%d: must be 2 or 3", legs);
+    if (!(earth_radius_m >= 0.0)) return fail(FS_E_INVALID, "negative or NaN radius");
+    double r = earth_radius_m == 0.0 ? 6371000.0 : earth_radius_m;
+    if (r > 1.1e8) return fail(FS_E_INVALID, "radius %.3g m: costs would overflow int32", r);
+    hipStream_t s = (hipStream_t)stream;
+
+    MissionPrep mp{};
+    double *buf = nullptr;
+    FS_HIP(hipMallocAsync((void **)&buf, sizeof(double) * 7 * (size_t)M, s));
+    mp.phi_p = buf;
+    mp.psi_p = buf + (size_t)M;
+    mp.cos_p = buf + 2 * (size_t)M;
+    mp.phi_d = buf + 3 * (size_t)M;
+    mp.psi_d = buf + 4 * (size_t)M;
+    mp.cos_d = buf + 5 * (size_t)M;
+    mp.pd = buf + 6 * (size_t)M;
+    double two_r = 2.0 * r;
+    dim3 g1((M + kBlock - 1) / kBlock);
+    k_mission_prep<<<g1, kBlock, 0, s>>>(mission_pd_deg, M, two_r, mp);
+    FS_HIP(hipGetLastError());
+    int32_t gy = (B + kBasesPerBlock - 1) / kBasesPerBlock;
+    dim3 g2((M + kBlock - 1) / kBlock, gy < 65535 ? gy : 65535);
+    k_cost_table<<<g2, kBlock, 0, s>>>(base_latlon_deg, B, M, two_r, legs, mp, C, Cf, ldc);
+    FS_HIP(hipGetLastError());
+    FS_HIP(hipFreeAsync(buf, s));
+    return FS_OK;
+}

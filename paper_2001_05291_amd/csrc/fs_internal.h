@@ -1,0 +1,159 @@
+// Internal declarations shared by the translation units of libfleetstage.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <vector>
+
+#include "fleetstage.h"
+
+namespace fs {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...);
+fs_status fail(fs_status code, const char *fmt, ...);
+
+#define FS_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t fs_e_ = (call);                                                     \
+        if (fs_e_ != hipSuccess)                                                       \
+            return ::fs::fail(FS_E_DEVICE, "%s failed: %s (%s:%d)", #call,             \
+                              hipGetErrorString(fs_e_), __FILE__, __LINE__);           \
+    } while (0)
+
+#define FS_TRY(expr)                                                                   \
+    do {                                                                               \
+        fs_status fs_s_ = (expr);                                                      \
+        if (fs_s_ != FS_OK) return fs_s_;                                              \
+    } while (0)
+
+// ---------------------------------------------------------------- timing
+
+// RAII bracket of one launch of a kernel group (0 sweep, 1 refresh,
+// 2 finalize) with HIP events when timing is enabled; a no-op otherwise.
+bool timing_on();
+class TimedLaunch {
+  public:
+    TimedLaunch(int group, hipStream_t s);
+    ~TimedLaunch();
+    TimedLaunch(const TimedLaunch &) = delete;
+    TimedLaunch &operator=(const TimedLaunch &) = delete;
+
+  private:
+    int group_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    bool armed_ = false;
+};
+
+// ---------------------------------------------------------------- limits
+
+constexpr int kMaxK = 1024;          // open slots handled by the sweep's LDS bins
+constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
+
+// ---------------------------------------------------------------- device state
+
+// Score of a placement: (coverage, distance of covered missions).
+struct Score {
+    int32_t cov;
+    int32_t pad;
+    int64_t dist;
+};
+
+// Best admissible move found by one sweep workgroup (or none: valid == 0).
+struct Candidate {
+    int32_t valid;
+    int32_t cov;
+    int32_t i_base, j_base;  // move: base i leaves, base j enters
+    int32_t i_slot, j_slot;  // positions in the open / closed lists
+    int64_t dist;
+};
+static_assert(sizeof(Candidate) == 32, "candidate layout");
+
+// Per-solve search state, resident in device memory so that every iteration
+// launches the same kernels with the same arguments.
+struct SolveState {
+    int32_t t;          // iterations completed
+    int32_t stopped;    // local search reached a local optimum
+    int32_t cur_cov;
+    int32_t best_cov;
+    int64_t cur_dist;
+    int64_t best_dist;
+    int32_t best_iter;
+    int32_t error;      // refreshed value disagreed with the executed move's score
+    int32_t err_iter;
+    int32_t pad;
+};
+
+// Accumulator of the per-placement sums: slot 0 is G (the placement's value),
+// slot 1 + k is L_k (value change if open slot k's base is removed and its
+// missions fall back to their second-nearest open base).  Two's complement in
+// unsigned 64-bit so that integer atomics add signed deltas exactly.
+struct Acc {
+    unsigned long long cov;
+    unsigned long long dist;
+};
+
+// Device buffers of one single-instance solve.
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+    int32_t *open = nullptr;        // K      slot -> base id
+    int32_t *closed = nullptr;      // B - K  slot -> base id
+    int32_t *tabu_until = nullptr;  // B
+    int32_t *b1 = nullptr;          // Mp     nearest open cost
+    int32_t *b2 = nullptr;          // Mp     second-nearest open cost
+    int32_t *o1 = nullptr;          // Mp     slot of the nearest open base
+    Acc *acc = nullptr;             // K + 1
+    Candidate *cand = nullptr;      // sweep workgroups
+    SolveState *st = nullptr;
+    int32_t *best_open = nullptr;   // K
+    int32_t *part_cov = nullptr;    // split partials: nsplit x nclosed x (K + 1)
+    int64_t *part_dist = nullptr;
+};
+
+// Launch geometry of the swap sweep.
+struct SweepPlan {
+    int J = 1;           // closed rows per workgroup
+    int nsplit = 1;      // mission chunks
+    int chunk = 0;       // missions per chunk (multiple of 4)
+    int ngroups = 0;     // row groups = ceil(nclosed / J)
+    int ncand = 0;       // candidates written per sweep
+    bool vec4 = true;    // 16-byte row loads
+};
+
+struct Problem {
+    const int32_t *C;
+    int64_t ldc;
+    int32_t B, M, K, R, T, N, mode;
+    int32_t Mp;          // M rounded up to a multiple of 4
+};
+
+SweepPlan plan_sweep(const Problem &pb);
+size_t workspace_bytes(const Problem &pb, const SweepPlan &plan);
+void carve_workspace(Workspace &ws, void *base, const Problem &pb, const SweepPlan &plan);
+
+// Stream-ordered launches (defined in tabu.hip).
+fs_status launch_setup(const Problem &pb, const SweepPlan &plan, const Workspace &ws,
+                       const int32_t *open_host, hipStream_t s);
+fs_status launch_refresh(const Problem &pb, const Workspace &ws, hipStream_t s);
+fs_status launch_init_score(const Problem &pb, const Workspace &ws, hipStream_t s);
+fs_status launch_sweep(const Problem &pb, const SweepPlan &plan, const Workspace &ws,
+                       int32_t *sc_cov, int64_t *sc_dist, hipStream_t s);
+fs_status launch_finalize(const Problem &pb, const SweepPlan &plan, const Workspace &ws,
+                          fs_trace_rec *trace, hipStream_t s);
+
+// Host-side validation helpers.
+fs_status check_table(const int32_t *C, int64_t ldc, int32_t B, int32_t M);
+fs_status check_open_list(const std::vector<int32_t> &ids, int32_t B);
+
+// Base ranking on the device (rank.hip): row sums, then the K smallest
+// (sum, id) in rank order.
+fs_status launch_sort_ids(const int32_t *ids, int32_t K, int32_t *out, hipStream_t s);
+fs_status launch_rank(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K,
+                      int32_t *order_out, int64_t *sums, hipStream_t s);
+
+}  // namespace fs

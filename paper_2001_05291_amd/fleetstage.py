@@ -1,0 +1,199 @@
+"""ctypes binding of libfleetstage.so (declared in include/fleetstage.h).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+provides device memory (CUDA/HIP tensors) and the current stream.  The binding
+fails loudly when the library has not been built; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfleetstage.so")
+
+FS_OK, FS_PENDING = 0, 1
+FS_E_INVALID, FS_E_NOMEM, FS_E_DEVICE = -1, -2, -3
+FS_E_BUDGET, FS_E_NOTFOUND, FS_E_CLOSED, FS_E_INTERNAL = -4, -5, -6, -7
+
+TRACE_DTYPE = np.dtype([("iter", "<i4"), ("out_base", "<i4"), ("in_base", "<i4"),
+                        ("moved", "<i4"), ("cur_cov", "<i4"), ("best_cov", "<i4"),
+                        ("cur_dist", "<i8"), ("best_dist", "<i8")])
+assert TRACE_DTYPE.itemsize == 40
+
+
+class FleetstageError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"fleetstage status {status}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tenure", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("range_m", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+class Score(ctypes.Structure):
+    _fields_ = [("coverage", ctypes.c_int32), ("best_iter", ctypes.c_int32),
+                ("distance", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loads it on first use; raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FleetstageError(FS_E_DEVICE, f"{LIB_PATH} is not built; run "
+                              "`python -m paper_2001_05291_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.fs_last_error.restype = ctypes.c_char_p
+    L.fs_last_error.argtypes = []
+    L.fs_version.restype = ctypes.c_char_p
+    L.fs_version.argtypes = []
+    L.fs_build_cost_table.restype = i32
+    L.fs_build_cost_table.argtypes = [vp, i32, vp, i32, f64, i32, vp, i64, vp, vp]
+    L.fs_rank_bases.restype = i32
+    L.fs_rank_bases.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp]
+    L.fs_move_scores.restype = i32
+    L.fs_move_scores.argtypes = [vp, i64, i32, i32, vp, i32, i32, vp, vp, vp]
+    L.fs_tabu_solve.restype = i32
+    L.fs_tabu_solve.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(Params), vp, vp,
+                                ctypes.POINTER(Score), vp, vp, vp]
+    L.fs_timing_enable.restype = i32
+    L.fs_timing_enable.argtypes = [i32]
+    L.fs_timing_read.restype = i32
+    L.fs_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != FS_OK:
+        raise FleetstageError(status, lib().fs_last_error().decode(errors="replace"))
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda/hip) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _table(C, M):
+    if C.dim() != 2 or C.dtype != torch.int32:
+        raise TypeError("cost table must be a 2-D int32 tensor (bases x pitch)")
+    B, ldc = C.shape
+    M = ldc if M is None else int(M)
+    return B, M, ldc
+
+
+def version() -> str:
+    return lib().fs_version().decode()
+
+
+def build_cost_table(bases, missions, earth_radius_m: float = 0.0, legs: int = 3,
+                     ldc: int | None = None, want_cf: bool = False, stream=None):
+    """C (int32, B x ldc) and optionally Cf (float64) from device coordinates:
+    bases (B, 2) and missions (M, 4) float64 degrees.  ldc defaults to M
+    rounded up to a multiple of 4 (16-byte aligned rows)."""
+    B, M = int(bases.shape[0]), int(missions.shape[0])
+    ldc = (M + 3) // 4 * 4 if ldc is None else int(ldc)
+    dev = bases.device
+    C = torch.empty((B, ldc), dtype=torch.int32, device=dev)
+    Cf = torch.empty((B, ldc), dtype=torch.float64, device=dev) if want_cf else None
+    _check(lib().fs_build_cost_table(_ptr(bases, torch.float64), B,
+                                     _ptr(missions, torch.float64), M, float(earth_radius_m),
+                                     int(legs), _ptr(C), ldc, _ptr(Cf), _stream(stream)))
+    return C, Cf
+
+
+def rank_bases(C, K: int, M: int | None = None, stream=None):
+    """(open ascending, order by rank, row sums) as device tensors."""
+    B, M, ldc = _table(C, M)
+    dev = C.device
+    op = torch.empty(K, dtype=torch.int32, device=dev)
+    order = torch.empty(K, dtype=torch.int32, device=dev)
+    sums = torch.empty(B, dtype=torch.int64, device=dev)
+    _check(lib().fs_rank_bases(_ptr(C), ldc, B, M, int(K), _ptr(op), _ptr(order), _ptr(sums),
+                               _stream(stream)))
+    return op, order, sums
+
+
+def move_scores(C, open_ids, range_m: int, M: int | None = None, stream=None):
+    """(cov, dist) device tensors K x B: value of open - open[k] + j for closed j."""
+    B, M, ldc = _table(C, M)
+    dev = C.device
+    op = open_ids.to(device=dev, dtype=torch.int32).contiguous()
+    K = int(op.numel())
+    cov = torch.empty((K, B), dtype=torch.int32, device=dev)
+    dist = torch.empty((K, B), dtype=torch.int64, device=dev)
+    _check(lib().fs_move_scores(_ptr(C), ldc, B, M, _ptr(op), K, int(range_m), _ptr(cov),
+                                _ptr(dist), _stream(stream)))
+    return cov, dist
+
+
+@dataclass
+class SolveResult:
+    best_open: torch.Tensor          # device int32 K, ascending
+    coverage: int
+    distance: int
+    best_iter: int
+    assign: torch.Tensor | None      # device int32 M
+    trace: np.ndarray | None         # host structured array (TRACE_DTYPE)
+
+
+def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int = 0,
+               init_open=None, M: int | None = None, want_assign: bool = True,
+               want_trace: bool = True, stream=None) -> SolveResult:
+    B, M, ldc = _table(C, M)
+    dev = C.device
+    p = Params(int(tenure), int(iterations), int(range_m), int(mode))
+    best = torch.empty(K, dtype=torch.int32, device=dev)
+    assign = torch.empty(M, dtype=torch.int32, device=dev) if want_assign else None
+    n = max(int(iterations), 0)
+    trace = torch.empty(max(n, 1) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=dev) \
+        if want_trace else None
+    init = None
+    if init_open is not None:
+        init = init_open.to(device=dev, dtype=torch.int32).contiguous()
+    sc = Score()
+    _check(lib().fs_tabu_solve(_ptr(C), ldc, B, M, int(K), ctypes.byref(p), _ptr(init),
+                               _ptr(best), ctypes.byref(sc), _ptr(assign),
+                               _ptr(trace) if n > 0 else None, _stream(stream)))
+    tr = None
+    if want_trace:
+        tr = trace[: n * TRACE_DTYPE.itemsize].cpu().numpy().view(TRACE_DTYPE)
+    return SolveResult(best, int(sc.coverage), int(sc.distance), int(sc.best_iter), assign, tr)
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every sweep / refresh / finalize launch with HIP events."""
+    _check(lib().fs_timing_enable(1 if on else 0))
+
+
+def timing_read(group: str):
+    """(total device ms, launches) recorded for a kernel group since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().fs_timing_read(group.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)

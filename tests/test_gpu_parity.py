@@ -1,0 +1,313 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Integer outputs must match bit for bit; the FP64 cost
+table within 1e-12 relative before rounding."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2001_05291_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import DEV, assert_trace_equal, instance_and_table, oracle_table, padded_table, to_dev  # noqa: E402
+
+fs = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global fs
+    from paper_2001_05291_amd import fleetstage
+    fs = fleetstage
+    fs.lib()
+    torch.cuda.init()
+    yield
+
+
+class env:
+    """Temporarily set launch-geometry overrides (read at every call)."""
+
+    def __init__(self, **kv):
+        self.kv = {k: str(v) for k, v in kv.items()}
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.kv}
+        os.environ.update(self.kv)
+
+    def __exit__(self, *a):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+# ------------------------------------------------------------------ cost table (A0)
+
+
+def check_cost_table(inst, legs=3, ldc=None):
+    Cg, Cfg = fs.build_cost_table(to_dev(inst.bases), to_dev(inst.missions), legs=legs,
+                                  ldc=ldc, want_cf=True)
+    M = inst.M
+    Cg = Cg[:, :M].cpu().numpy()
+    Cfg = Cfg[:, :M].cpu().numpy()
+    Co, Cfo = oracle.cost_table(inst.bases, inst.missions, legs=legs)
+    rel = np.abs(Cfg - Cfo) / np.maximum(Cfo, 1.0)
+    assert rel.max() <= 1e-12, rel.max()
+    mism = np.nonzero(Cg != Co)
+    # an int32 difference is only allowed where both FP64 values straddle a
+    # rounding boundary within the tolerance
+    for b, m in zip(*mism):
+        assert abs(int(Cg[b, m]) - int(Co[b, m])) == 1
+        frac = Cfo[b, m] - np.floor(Cfo[b, m])
+        assert abs(frac - 0.5) <= 1e-12 * Cfo[b, m] + 1e-9
+    return len(mism[0])
+
+
+def test_cost_table_config1():
+    assert check_cost_table(synth.config_instance(1)) == 0
+
+
+def test_cost_table_ragged_and_two_legs():
+    inst = synth.make_instance(seed=21, B=37, H=90, M=1003)
+    check_cost_table(inst, legs=3)
+    check_cost_table(inst, legs=2, ldc=1009)
+
+
+def test_cost_table_full_size_sampled():
+    """Largest single-GPU table (4,000 bases x 100,000 missions) built on the
+    GPU; sampled base rows x mission columns checked against the oracle."""
+    c = synth.CONFIGS[3]
+    inst = synth.config_instance(3)
+    Cg, Cfg = fs.build_cost_table(to_dev(inst.bases), to_dev(inst.missions), want_cf=True)
+    rng = np.random.default_rng(0)
+    bi = np.sort(rng.choice(c["B"], 48, replace=False))
+    mi = np.sort(rng.choice(c["M"], 3000, replace=False))
+    Cs = Cg[to_dev(bi, torch.int64)][:, to_dev(mi, torch.int64)].cpu().numpy()
+    Cfs = Cfg[to_dev(bi, torch.int64)][:, to_dev(mi, torch.int64)].cpu().numpy()
+    Co, Cfo = oracle.cost_table(inst.bases[bi], inst.missions[mi])
+    assert (np.abs(Cfs - Cfo) / Cfo).max() <= 1e-12
+    assert int((Cs != Co).sum()) <= 2
+    del Cg, Cfg
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ rank (A1)
+
+
+@pytest.mark.parametrize("ldc_pad", [0, 4, 1])
+def test_rank_matches_oracle(ldc_pad):
+    rng = np.random.default_rng(2 + ldc_pad)
+    cases = [oracle_table(synth.config_instance(1)), oracle_table(synth.config_instance(2))]
+    cases += [rng.integers(0, 3, size=(300, 257)).astype(np.int32)]   # many equal sums
+    for C in cases:
+        B, M = C.shape
+        ldc = M + ldc_pad
+        Cd = padded_table(C, ldc)
+        for K in (1, 5, min(B, 30), B):
+            op, order, sums = fs.rank_bases(Cd, K, M=M)
+            o_open, o_order, o_sums = oracle.rank_bases(C, K)
+            assert np.array_equal(sums.cpu().numpy(), o_sums)
+            assert np.array_equal(order.cpu().numpy(), o_order)
+            assert np.array_equal(op.cpu().numpy(), o_open)
+
+
+# ------------------------------------------------------------------ move scores (A2, A3)
+
+
+def check_scores(C, S, R, ldc=None):
+    B, M = C.shape
+    Cd = padded_table(C, ldc or M)
+    cov, dist = fs.move_scores(Cd, torch.tensor(S, dtype=torch.int32), R, M=M)
+    ocov, odist = oracle.move_scores(C, np.array(S, dtype=np.int32), R)
+    assert np.array_equal(cov.cpu().numpy(), ocov)
+    assert np.array_equal(dist.cpu().numpy(), odist)
+
+
+def test_move_scores_config1_and_2():
+    for cfg in (1, 2):
+        c = synth.CONFIGS[cfg]
+        _, C = instance_and_table(cfg)
+        S = oracle.rank_bases(C, c["K"])[0]
+        check_scores(C, S.tolist(), c["R"])
+
+
+@pytest.mark.parametrize("J,split", [(1, 1), (2, 3), (4, 1), (8, 5), (1, 7)])
+def test_move_scores_launch_geometries(J, split):
+    inst = synth.make_instance(seed=31, B=90, H=200, M=4103)
+    C = oracle_table(inst)
+    rng = np.random.default_rng(J * 10 + split)
+    S = rng.choice(90, 11, replace=False).tolist()
+    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
+        check_scores(C, S, 1_000_000, ldc=4104)   # 16-byte rows
+        check_scores(C, S, 1_000_000)             # 4-byte rows (ldc % 4 != 0)
+
+
+def test_move_scores_random_small():
+    rng = np.random.default_rng(41)
+    for trial in range(40):
+        B = int(rng.integers(2, 40))
+        M = int(rng.integers(1, 300))
+        K = int(rng.integers(1, B))
+        C = rng.integers(1, 2000, size=(B, M)).astype(np.int32)
+        if trial % 3 == 0:
+            C = rng.integers(1, 6, size=(B, M)).astype(np.int32)    # ties everywhere
+        R = int(rng.integers(0, 2100))
+        S = rng.choice(B, K, replace=False).tolist()
+        check_scores(C, S, R, ldc=M + int(rng.integers(0, 5)))
+
+
+# ------------------------------------------------------------------ tabu search (A4-A6)
+
+
+def run_both(C, K, R, T, N, mode=0, init=None, ldc=None):
+    B, M = C.shape
+    Cd = padded_table(C, ldc or M)
+    init_d = None if init is None else torch.tensor(init, dtype=torch.int32)
+    g = fs.tabu_solve(Cd, K, R, T, N, mode=mode, init_open=init_d, M=M)
+    o = oracle.tabu(C, K, R, T, N, mode=mode, init_open=init)
+    return g, o
+
+
+def assert_same_result(g, o, C, R):
+    assert np.array_equal(g.best_open.cpu().numpy(), o.best_open)
+    assert (g.coverage, g.distance, g.best_iter) == (o.coverage, o.distance, o.best_iter)
+    if g.trace is not None:
+        assert_trace_equal(g.trace, o)
+    if g.assign is not None:
+        assert np.array_equal(g.assign.cpu().numpy(), oracle.assign(C, o.best_open, R))
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_tabu_full_trace_configs(cfg):
+    c = synth.CONFIGS[cfg]
+    _, C = instance_and_table(cfg)
+    g, o = run_both(C, c["K"], c["R"], c["T"], c["N"], ldc=(c["M"] + 3) // 4 * 4)
+    assert_same_result(g, o, C, c["R"])
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_local_search_configs(cfg):
+    c = synth.CONFIGS[cfg]
+    _, C = instance_and_table(cfg)
+    g, o = run_both(C, c["K"], c["R"], c["T"], c["N"], mode=1)
+    assert_same_result(g, o, C, c["R"])
+
+
+def test_tabu_golden_fixtures_on_gpu():
+    import json
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    for name in ("tabu_aspiration.json", "tabu_coverage.json", "tabu_zero_range.json"):
+        fx = json.load(open(os.path.join(gdir, name)))
+        C = np.array(fx["C"], dtype=np.int32)
+        for run in fx["runs"]:
+            g, o = run_both(C, fx["K"], fx["R"], run["T"], run["N"], mode=run["mode"],
+                            init=fx.get("init_open"))
+            assert g.best_open.cpu().numpy().tolist() == run["best_open"]
+            assert (g.coverage, g.distance, g.best_iter) == (run["coverage"], run["distance"],
+                                                            run["best_iter"])
+            assert g.trace["out_base"].tolist() == run["out"]
+            assert g.trace["in_base"].tolist() == run["in"]
+            assert g.trace["cur_dist"].tolist() == run["cur_dist"]
+
+
+def test_tabu_random_instances():
+    rng = np.random.default_rng(51)
+    for trial in range(30):
+        B = int(rng.integers(2, 60))
+        M = int(rng.integers(1, 700))
+        K = int(rng.integers(1, B + 1))
+        C = rng.integers(1, 5000, size=(B, M)).astype(np.int32)
+        if trial % 4 == 0:
+            C = rng.integers(1, 8, size=(B, M)).astype(np.int32)
+        R = int(rng.integers(0, 5200))
+        T = int(rng.integers(0, 12))
+        N = int(rng.integers(0, 40))
+        mode = int(trial % 5 == 0)
+        init = None if trial % 2 else rng.choice(B, K, replace=False).tolist()
+        g, o = run_both(C, K, R, T, N, mode=mode, init=init, ldc=M + int(rng.integers(0, 4)))
+        assert_same_result(g, o, C, R)
+
+
+def test_special_cases():
+    rng = np.random.default_rng(61)
+    C = rng.integers(1, 100, size=(12, 50)).astype(np.int32)
+    # every base open: no move, value of the full set
+    g, o = run_both(C, 12, 80, 3, 6)
+    assert_same_result(g, o, C, 80)
+    assert g.trace["moved"].sum() == 0
+    # zero range: nothing covered
+    g, o = run_both(C, 3, 0, 2, 9)
+    assert_same_result(g, o, C, 0)
+    assert g.coverage == 0 and g.distance == 0
+    # one vehicle
+    g, o = run_both(C, 1, 90, 4, 5)
+    assert_same_result(g, o, C, 90)
+    # no iterations
+    g, o = run_both(C, 4, 90, 4, 0)
+    assert_same_result(g, o, C, 90)
+
+
+def test_plans_are_bit_identical():
+    """The result does not depend on the sweep's launch geometry."""
+    c = synth.CONFIGS[2]
+    _, C = instance_and_table(2)
+    Cd = padded_table(C, c["M"])
+    ref = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
+    for J, split in ((1, 1), (2, 4), (4, 9), (8, 2)):
+        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
+            g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
+        assert np.array_equal(g.trace, ref.trace)
+        assert np.array_equal(g.best_open.cpu().numpy(), ref.best_open.cpu().numpy())
+
+
+def test_full_size_prefix_and_invariants():
+    """Largest single-GPU instance (4,000 bases, 100,000 missions, 64
+    vehicles): the first iterations equal the oracle's; every record of the
+    200-iteration trace is consistent with a recount of its placement."""
+    c = synth.CONFIGS[3]
+    inst = synth.config_instance(3)
+    C = oracle_table(inst)
+    Cd = to_dev(C)
+    g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], c["N"])
+    n0 = 3
+    o = oracle.tabu(C, c["K"], c["R"], c["T"], n0)
+    assert_trace_equal(g.trace, o, n=n0)
+    # replay: placement after each move, recounted on the device with torch
+    S = list(oracle.rank_bases(C, c["K"])[0])
+    R = c["R"]
+    best = None
+    for t in range(c["N"]):
+        rec = g.trace[t]
+        if rec["moved"]:
+            S[S.index(int(rec["out_base"]))] = int(rec["in_base"])
+        if t % 25 == 0 or t == c["N"] - 1:
+            v = Cd[torch.tensor(S, device=DEV, dtype=torch.int64)].min(dim=0).values.to(torch.int64)
+            cov = int((v <= R).sum())
+            dist = int(torch.where(v <= R, v, torch.zeros_like(v)).sum())
+            assert (cov, dist) == (int(rec["cur_cov"]), int(rec["cur_dist"])), t
+        cur = (int(rec["cur_cov"]), -int(rec["cur_dist"]))
+        best = cur if best is None or cur > best else best
+        assert (int(rec["best_cov"]), -int(rec["best_dist"])) >= best
+    assert g.coverage == int(g.trace["best_cov"][-1])
+    assert g.distance == int(g.trace["best_dist"][-1])
+    del Cd
+    torch.cuda.empty_cache()
+
+
+def test_invalid_arguments_leave_outputs_untouched():
+    C = np.ones((5, 8), dtype=np.int32)
+    Cd = to_dev(C)
+    with pytest.raises(fs.FleetstageError) as e:
+        fs.tabu_solve(Cd, 6, 10, 1, 3)
+    assert e.value.status == fs.FS_E_INVALID
+    with pytest.raises(fs.FleetstageError) as e:
+        fs.tabu_solve(Cd, 2, 10, 1, 3, init_open=torch.tensor([1, 1], dtype=torch.int32))
+    assert e.value.status == fs.FS_E_INVALID
+    with pytest.raises(fs.FleetstageError) as e:
+        fs.tabu_solve(Cd, 2, -1, 1, 3)
+    assert e.value.status == fs.FS_E_INVALID
