@@ -163,6 +163,35 @@ fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int
                         int32_t *best_open_out, fs_score *score_out,
                         int32_t *assign_out, fs_trace_rec *trace_out, void *stream);
 
+/* One instance of a batch (host struct; pointers are device pointers).
+ *   C, ldc, B, M, K, range_m  as for fs_tabu_solve
+ *   init_open      device K ids, or NULL (base ranking)
+ *   best_open_out  device K int32, best placement in ascending id order
+ *   assign_out     device M int32 (as in fs_tabu_solve), or NULL
+ *   trace_out      device p->iterations records, or NULL */
+typedef struct {
+    const int32_t *C;
+    int64_t ldc;
+    int32_t B, M, K, range_m;
+    const int32_t *init_open;
+    int32_t *best_open_out;
+    int32_t *assign_out;
+    fs_trace_rec *trace_out;
+} fs_instance;
+
+/* Tabu search (Section 4.3, Algorithm 3) of n independent instances of
+ * uneven size in one launch set: every kernel of an iteration covers all
+ * instances through a tile table, so small and large instances share the GPU.
+ * Tenure, iterations and mode come from p (p->range_m is ignored: each
+ * instance has its own range).  Each instance's result, score and trace are
+ * identical to fs_tabu_solve on that instance alone.
+ *   inst        host array of n instances (each B <= 32768, K <= 1024)
+ *   scores_out  host array of n scores
+ * Errors: FS_E_INVALID names the first offending instance; FS_E_INTERNAL as
+ * for fs_tabu_solve.  Synchronises the stream before returning. */
+fs_status fs_tabu_solve_batch(const fs_instance *inst, int32_t n, const fs_params *p,
+                              fs_score *scores_out, void *stream);
+
 /* Diagnostics: device time of the search kernels, for roofline reporting.
  * While enabled (on != 0), every launch of a kernel group is bracketed by a
  * pair of HIP events recorded on the stream it is launched on; groups are

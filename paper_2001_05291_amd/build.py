@@ -36,7 +36,8 @@ EXTRA = {
     # products and sums of the haversine rounded one by one, in source order
     "cost_table.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["common.cpp", "timing.cpp", "cost_table.hip", "rank.hip", "tabu.hip"]
+SOURCES = ["common.cpp", "timing.cpp", "cost_table.hip", "rank.hip", "engine.hip",
+           "launchset.hip", "tabu.hip", "batch.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

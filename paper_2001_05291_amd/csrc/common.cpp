@@ -52,6 +52,43 @@ fs_status check_open_list(const std::vector<int32_t> &ids, int32_t B)
     return FS_OK;
 }
 
+fs_status check_problem(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K, int32_t R)
+{
+    FS_TRY(check_table(C, ldc, B, M));
+    if (K < 1 || K > B) return fail(FS_E_INVALID, "K=%d must be in [1, B=%d]", K, B);
+    if (K > kMaxK) return fail(FS_E_INVALID, "K=%d exceeds the supported %d vehicles", K, kMaxK);
+    if (R < 0 || R == INT32_MAX) return fail(FS_E_INVALID, "range %d outside [0, INT32_MAX)", R);
+    if ((int64_t)M + 3 > INT32_MAX) return fail(FS_E_INVALID, "M=%d too large", M);
+    return FS_OK;
+}
+
+fs_status check_params(const fs_params *p)
+{
+    if (!p) return fail(FS_E_INVALID, "params pointer is NULL");
+    if (p->tenure < 0) return fail(FS_E_INVALID, "tenure %d < 0", p->tenure);
+    if (p->iterations < 0) return fail(FS_E_INVALID, "iterations %d < 0", p->iterations);
+    if ((int64_t)p->iterations + p->tenure >= INT32_MAX)
+        return fail(FS_E_INVALID, "iterations + tenure overflow int32");
+    if (p->mode != 0 && p->mode != 1) return fail(FS_E_INVALID, "mode %d not 0 or 1", p->mode);
+    return FS_OK;
+}
+
+fs_status fetch_open_list(const int32_t *dev, int32_t K, int32_t B, std::vector<int32_t> &out,
+                          hipStream_t s)
+{
+    out.assign(K, 0);
+    FS_HIP(hipMemcpyAsync(out.data(), dev, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    return check_open_list(out, B);
+}
+
+fs_status prefix_error(fs_status code, const char *what, int32_t index)
+{
+    char copy[sizeof g_msg];
+    snprintf(copy, sizeof copy, "%s", g_msg);
+    return fail(code, "%s %d: %s", what, index, copy);
+}
+
 }  // namespace fs
 
 extern "C" const char *fs_last_error(void) { return fs::g_msg; }

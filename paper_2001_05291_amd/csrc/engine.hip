@@ -1,0 +1,1171 @@
+// Tabu search over swap moves on gfx950 (Section 4.3, Algorithm 3; local-search
+// baseline of Section 4.2, Algorithm 2) for any set of instances.
+//
+// Every check of Algorithms 2-3 recomputes the total distance of a changed
+// placement, O(M) per move.  Here one iteration scores all K*(B-K) swaps
+// exactly with one streaming pass over the closed rows of the cost table:
+//
+//   per mission m:  b1 = nearest open cost, o1 = its slot, b2 = second-nearest
+//   G   = sum_m g(b1)                        (value of the placement)
+//   L_i = sum_{o1(m)=i} g(b2) - g(b1)        (value change if i is closed)
+//   score(i, j) = G + L_i + sum_m [g(min(c, b1)) - g(b1)]
+//                         + sum_{o1(m)=i, c < b2} [g(max(c, b1)) - g(b2)]
+//   with c = C[j][m] and g(v) = (v <= R) ? (1, v) : (0, 0)
+//
+// which equals the value of S - i + j.  Both sums vanish unless c < b2, so a
+// row element costs a load and a compare on the common path; the rare path
+// adds the first sum to per-lane registers and the second to an LDS bin of
+// the out-slot o1(m).  One read of row j thus serves all K out-bases.
+//
+// Kernels of one iteration, each over a tile table spanning every instance of
+// the launch set:
+//   k_sweep    J closed rows x one mission chunk per workgroup; when an
+//              instance's missions are not split it also scores its J*K moves,
+//              keeps the best admissible one, and the last of the instance's
+//              workgroups to finish performs the argmax and applies the move
+//              (tabu list, best-so-far, trace);
+//   k_score    merges the chunk partials of split instances, then as above;
+//   k_refresh  nearest / second-nearest open cost of every mission, and the
+//              sums G and L_k, for the new placement.
+// All search state lives in device memory, so the host enqueues the same
+// launches every iteration.
+#include <algorithm>
+#include <cstdlib>
+
+#include "engine.h"
+
+namespace fs {
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ bool better(int32_t ca, int64_t da, int32_t cb, int64_t db)
+{
+    return ca != cb ? ca > cb : da < db;
+}
+
+// Move order: coverage desc, distance asc, out-base asc, in-base asc.
+__device__ __forceinline__ bool cand_better(const Candidate &a, const Candidate &b)
+{
+    if (!a.valid) return false;
+    if (!b.valid) return true;
+    if (a.cov != b.cov) return a.cov > b.cov;
+    if (a.dist != b.dist) return a.dist < b.dist;
+    if (a.i_base != b.i_base) return a.i_base < b.i_base;
+    return a.j_base < b.j_base;
+}
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ Candidate shfl_xor_cand(const Candidate &c, int off)
+{
+    Candidate o;
+    o.valid = __shfl_xor(c.valid, off, 64);
+    o.cov = __shfl_xor(c.cov, off, 64);
+    o.i_base = __shfl_xor(c.i_base, off, 64);
+    o.j_base = __shfl_xor(c.j_base, off, 64);
+    o.i_slot = __shfl_xor(c.i_slot, off, 64);
+    o.j_slot = __shfl_xor(c.j_slot, off, 64);
+    o.dist = __shfl_xor(c.dist, off, 64);
+    return o;
+}
+
+// Best candidate of the workgroup under the move order (a total order, so the
+// result does not depend on the reduction order); valid in every thread.
+__device__ Candidate block_best(Candidate c, Candidate *s_red /* kBlock/64 + 1 */)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        Candidate o = shfl_xor_cand(c, off);
+        if (cand_better(o, c)) c = o;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) s_red[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Candidate b = s_red[0];
+        for (int w = 1; w < kBlock / 64; ++w)
+            if (cand_better(s_red[w], b)) b = s_red[w];
+        s_red[kBlock / 64] = b;
+    }
+    __syncthreads();
+    return s_red[kBlock / 64];
+}
+
+// G (k = 0) or L_{k-1}: sum of the accumulator stripes.
+__device__ __forceinline__ void acc_sum(const Acc *acc, int32_t K, int32_t k, int32_t &c,
+                                        int64_t &dd)
+{
+    u64 sc = 0, sd = 0;
+#pragma unroll
+    for (int s = 0; s < kStripes; ++s) {
+        sc += acc[s * (K + 1) + k].cov;
+        sd += acc[s * (K + 1) + k].dist;
+    }
+    c = (int32_t)(int64_t)sc;
+    dd = (int64_t)sd;
+}
+
+__device__ __forceinline__ bool idle(const InstDesc &d) { return !d.active || d.st->t >= d.N; }
+
+// ---------------------------------------------------------------- setup
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kBlock)
+        p[q] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i64(int64_t *p, int64_t n, int64_t v)
+{
+    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kBlock)
+        p[q] = v;
+}
+
+// grid = ninst x per_inst blocks: tabu list, accumulators, state, counter.
+__global__ __launch_bounds__(kBlock) void k_reset(const InstDesc *__restrict__ descs, int per_inst)
+{
+    const int inst = blockIdx.x / per_inst, blk = blockIdx.x - inst * per_inst;
+    const InstDesc &d = descs[inst];
+    if (!d.active) return;
+    const int32_t q = blk * kBlock + threadIdx.x;
+    if (q < d.B) d.tabu_until[q] = 0;
+    if (q < kStripes * (d.K + 1)) {
+        d.acc[q].cov = 0;
+        d.acc[q].dist = 0;
+    }
+    if (q == 0) {
+        *d.st = SolveState{};
+        *d.counter = 0u;
+    }
+}
+
+// ---------------------------------------------------------------- refresh (A2)
+
+// One workgroup = 64 missions (one per lane); the four waves split the open
+// slots (k = wave, wave + 4, ...), issue their loads together, and the partial
+// nearest / second-nearest are merged in LDS.  Ties in the nearest cost go to
+// the lower base id.  G and L_k are summed in LDS, then added with integer
+// atomics into one of kStripes accumulator copies (exact in any order).
+__global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__ descs,
+                                                    const Tile *__restrict__ tiles, int initial)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const InstDesc &d = descs[tl.inst];
+    if (!d.active) return;
+    if (!initial && (d.st->stopped || d.st->t >= d.N)) return;
+    const int32_t K = d.K, M = d.M, R = d.R;
+    const int64_t ldc = d.ldc;
+    extern __shared__ __align__(16) unsigned char smem[];
+    u64 *s_cov = reinterpret_cast<u64 *>(smem);
+    u64 *s_dist = s_cov + (K + 1);
+    int32_t *s_open = reinterpret_cast<int32_t *>(s_dist + (K + 1));
+    __shared__ int32_t p_v1[kBlock / 64][64], p_i1[kBlock / 64][64], p_s1[kBlock / 64][64],
+        p_v2[kBlock / 64][64];
+    for (int k = threadIdx.x; k <= K; k += kBlock) {
+        s_cov[k] = 0;
+        s_dist[k] = 0;
+    }
+    for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = d.open[k];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t m = tl.g * kRefreshMissions + lane;
+    int32_t v1 = INT32_MAX, i1 = INT32_MAX, s1 = 0, v2 = INT32_MAX;
+    if (m < M) {
+        const int32_t *col = d.C + m;
+        constexpr int W = kBlock / 64, UNR = 16;
+        for (int32_t k0 = wave; k0 < K; k0 += W * UNR) {
+            int32_t c[UNR], id[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int32_t k = k0 + W * u;
+                id[u] = k < K ? s_open[k] : 0;
+                c[u] = k < K ? col[(int64_t)id[u] * ldc] : INT32_MAX;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int32_t k = k0 + W * u;
+                if (k < K) {
+                    if (c[u] < v1 || (c[u] == v1 && id[u] < i1)) {
+                        v2 = v1;
+                        v1 = c[u];
+                        i1 = id[u];
+                        s1 = k;
+                    } else if (c[u] < v2) {
+                        v2 = c[u];
+                    }
+                }
+            }
+        }
+    }
+    p_v1[wave][lane] = v1;
+    p_i1[wave][lane] = i1;
+    p_s1[wave][lane] = s1;
+    p_v2[wave][lane] = v2;
+    __syncthreads();
+    if (wave == 0) {
+        v1 = p_v1[0][lane];
+        i1 = p_i1[0][lane];
+        s1 = p_s1[0][lane];
+        v2 = p_v2[0][lane];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) {
+            const int32_t bv1 = p_v1[w][lane], bi1 = p_i1[w][lane];
+            if (bv1 < v1 || (bv1 == v1 && bi1 < i1)) {
+                v2 = min(v1, p_v2[w][lane]);
+                v1 = bv1;
+                i1 = bi1;
+                s1 = p_s1[w][lane];
+            } else {
+                v2 = min(v2, bv1);
+            }
+        }
+        int32_t g1c = 0, g1d = 0;
+        if (m < M) {
+            d.b1[m] = v1;
+            d.b2[m] = v2;
+            d.o1[m] = s1;
+            g1c = v1 <= R;
+            g1d = g1c ? v1 : 0;
+            const int32_t g2c = v2 <= R;
+            const int32_t g2d = g2c ? v2 : 0;
+            const int32_t dc = g2c - g1c, dd = g2d - g1d;
+            if (dc | dd) {
+                atomicAdd(&s_cov[1 + s1], (u64)(int64_t)dc);
+                atomicAdd(&s_dist[1 + s1], (u64)(int64_t)dd);
+            }
+        } else if (m < d.Mp) {
+            // padding missions: a sentinel below every cost, so the sweep skips them
+            d.b1[m] = INT32_MIN;
+            d.b2[m] = INT32_MIN;
+            d.o1[m] = 0;
+        }
+        const int32_t wc = wave_sum_i32(g1c);
+        const int64_t wd = wave_sum_i64((int64_t)g1d);
+        if (lane == 0) {
+            atomicAdd(&s_cov[0], (u64)(int64_t)wc);
+            atomicAdd(&s_dist[0], (u64)wd);
+        }
+    }
+    __syncthreads();
+    Acc *acc = d.acc + (blockIdx.x & (kStripes - 1)) * (K + 1);
+    for (int k = threadIdx.x; k <= K; k += kBlock) {
+        const u64 c = s_cov[k], dd = s_dist[k];
+        if (c | dd) {
+            atomicAdd(&acc[k].cov, c);
+            atomicAdd(&acc[k].dist, dd);
+        }
+    }
+}
+
+// cur = best = G of the initial placement; best_open = open.  grid = ninst.
+__global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restrict__ descs)
+{
+    const InstDesc &d = descs[blockIdx.x];
+    if (!d.active) return;
+    if (threadIdx.x == 0) {
+        int32_t gc;
+        int64_t gd;
+        acc_sum(d.acc, d.K, 0, gc, gd);
+        SolveState s{};
+        s.cur_cov = gc;
+        s.cur_dist = gd;
+        s.best_cov = gc;
+        s.best_dist = gd;
+        *d.st = s;
+    }
+    for (int k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[k];
+}
+
+// ---------------------------------------------------------------- finish (A4 global, A5)
+
+// Trace record of an iteration without a move (local search already stopped).
+__device__ void record_no_move(const InstDesc &d)
+{
+    SolveState *st = d.st;
+    const int32_t t = st->t + 1;
+    if (d.trace) {
+        fs_trace_rec rec;
+        rec.iter = t;
+        rec.out_base = -1;
+        rec.in_base = -1;
+        rec.moved = 0;
+        rec.cur_cov = st->cur_cov;
+        rec.best_cov = st->best_cov;
+        rec.cur_dist = st->cur_dist;
+        rec.best_dist = st->best_dist;
+        d.trace[t - 1] = rec;
+    }
+    st->t = t;
+}
+
+// One workgroup: argmax over the instance's candidates, then apply the move,
+// update the tabu list, the best-so-far and the trace, and clear the
+// accumulators and the counter for the next iteration.
+__device__ void finish_iteration(const InstDesc &d, Candidate *s_red, int32_t *s_flag)
+{
+    SolveState *st = d.st;
+    const int32_t ncand = d.ngroups > 0 ? d.ngroups : 1;
+    Candidate best{};
+    for (int32_t q = threadIdx.x; q < ncand; q += kBlock) {
+        const Candidate c = d.cand[q];
+        if (cand_better(c, best)) best = c;
+    }
+    best = block_best(best, s_red);
+    if (threadIdx.x == 0) {
+        const int32_t t = st->t + 1;
+        int32_t moved = 0, improved = 0;
+        // the refreshed value of the current placement must equal the score
+        // the previous move was chosen with
+        int32_t gc;
+        int64_t gd;
+        acc_sum(d.acc, d.K, 0, gc, gd);
+        if ((gc != st->cur_cov || gd != st->cur_dist) && !st->error) {
+            st->error = 1;
+            st->err_iter = t;
+        }
+        if (best.valid) {
+            d.open[best.i_slot] = best.j_base;
+            d.closed[best.j_slot] = best.i_base;
+            d.tabu_until[best.i_base] = t + d.T;
+            d.tabu_until[best.j_base] = t + d.T;
+            st->cur_cov = best.cov;
+            st->cur_dist = best.dist;
+            moved = 1;
+            if (better(best.cov, best.dist, st->best_cov, st->best_dist)) {
+                st->best_cov = best.cov;
+                st->best_dist = best.dist;
+                st->best_iter = t;
+                improved = 1;
+            }
+        } else if (d.mode == 1) {
+            st->stopped = 1;
+        }
+        if (d.trace) {
+            fs_trace_rec rec;
+            rec.iter = t;
+            rec.out_base = moved ? best.i_base : -1;
+            rec.in_base = moved ? best.j_base : -1;
+            rec.moved = moved;
+            rec.cur_cov = st->cur_cov;
+            rec.best_cov = st->best_cov;
+            rec.cur_dist = st->cur_dist;
+            rec.best_dist = st->best_dist;
+            d.trace[t - 1] = rec;
+        }
+        st->t = t;
+        *s_flag = improved;
+    }
+    __syncthreads();
+    if (*s_flag)
+        for (int32_t k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[k];
+    for (int32_t q = threadIdx.x; q < kStripes * (d.K + 1); q += kBlock) {
+        d.acc[q].cov = 0;
+        d.acc[q].dist = 0;
+    }
+    if (threadIdx.x == 0) *d.counter = 0u;
+}
+
+// Standalone finish (grid = ninst): instances without fused finishing.
+__global__ __launch_bounds__(kBlock) void k_finalize(const InstDesc *__restrict__ descs)
+{
+    __shared__ Candidate s_red[kBlock / 64 + 1];
+    __shared__ int32_t s_flag;
+    const InstDesc &d = descs[blockIdx.x];
+    if (idle(d)) return;
+    if (d.st->stopped) {
+        if (threadIdx.x == 0) record_no_move(d);
+        return;
+    }
+    finish_iteration(d, s_red, &s_flag);
+}
+
+// ---------------------------------------------------------------- sweep (A3, A4 local)
+
+__device__ __forceinline__ void visit(int32_t c, int32_t b1, int32_t b2, int32_t o1, int32_t g1c,
+                                      int32_t g1d, int32_t g2c, int32_t g2d, int32_t R,
+                                      int32_t &t1c, int64_t &t1d, int32_t *__restrict__ bc,
+                                      u64 *__restrict__ bd)
+{
+    if (c < b2) {
+        const int32_t v1 = min(c, b1);
+        const int32_t u = max(c, b1);
+        const int32_t cv = v1 <= R;
+        t1c += cv - g1c;
+        t1d += (int64_t)((cv ? v1 : 0) - g1d);
+        const int32_t cu = u <= R;
+        const int32_t dc = cu - g2c;
+        const int32_t dd = (cu ? u : 0) - g2d;
+        if (dc | dd) {
+            atomicAdd(bc + o1, dc);
+            atomicAdd(bd + o1, (u64)(int64_t)dd);
+        }
+    }
+}
+
+// LDS of the sweep / score kernels for J rows and up to Kmax slots.
+__host__ __device__ constexpr size_t sweep_lds_bytes(int J, int Kmax)
+{
+    return (size_t)J * Kmax * 12 + (size_t)(Kmax + 1) * 12 + (size_t)Kmax * 4 + 16;
+}
+
+struct SweepLds {
+    u64 *bd;       // J*K bins: distance
+    int64_t *Ld;   // K+1: G, L_k distance
+    int32_t *bc;   // J*K bins: coverage
+    int32_t *Lc;   // K+1: G, L_k coverage
+    int32_t *open; // K
+};
+
+__device__ __forceinline__ SweepLds carve_lds(unsigned char *smem, int J, int K)
+{
+    SweepLds s;
+    s.bd = reinterpret_cast<u64 *>(smem);
+    s.Ld = reinterpret_cast<int64_t *>(s.bd + J * K);
+    s.bc = reinterpret_cast<int32_t *>(s.Ld + (K + 1));
+    s.Lc = s.bc + J * K;
+    s.open = s.Lc + (K + 1);
+    return s;
+}
+
+// Scores of the J x K moves of row group g from the per-row common sums
+// (t1c, t1d) and the per-(row, out-slot) bins; writes the optional full score
+// table and the group's best admissible candidate.
+__device__ void score_group(const InstDesc &d, int J, int32_t g, const int32_t *s_jrow,
+                            const SweepLds &L, const int32_t *t1c, const int64_t *t1d,
+                            Candidate *s_red)
+{
+    const int32_t K = d.K;
+    for (int32_t k = threadIdx.x; k <= K; k += kBlock) {
+        int32_t c;
+        int64_t dd;
+        acc_sum(d.acc, K, k, c, dd);
+        L.Lc[k] = c;
+        L.Ld[k] = dd;
+    }
+    for (int32_t k = threadIdx.x; k < K; k += kBlock) L.open[k] = d.open[k];
+    __syncthreads();
+    const SolveState *st = d.st;
+    const int32_t t = st->t + 1;
+    const int32_t cur_c = st->cur_cov, best_c = st->best_cov;
+    const int64_t cur_d = st->cur_dist, best_d = st->best_dist;
+    const int32_t Gc = L.Lc[0];
+    const int64_t Gd = L.Ld[0];
+    Candidate mine{};
+    for (int32_t idx = threadIdx.x; idx < J * K; idx += kBlock) {
+        const int32_t r = idx / K, k = idx - r * K;
+        const int32_t js = g * J + r;
+        if (js >= d.nclosed) continue;
+        const int32_t cov = Gc + L.Lc[1 + k] + t1c[r] + L.bc[idx];
+        const int64_t dist = Gd + L.Ld[1 + k] + t1d[r] + (int64_t)L.bd[idx];
+        const int32_t i = L.open[k], j = s_jrow[r];
+        if (d.sc_cov) {
+            d.sc_cov[(int64_t)k * d.B + j] = cov;
+            d.sc_dist[(int64_t)k * d.B + j] = dist;
+        }
+        bool adm;
+        if (d.mode == 1)
+            adm = better(cov, dist, cur_c, cur_d);
+        else
+            adm = (d.tabu_until[i] < t && d.tabu_until[j] < t) || better(cov, dist, best_c, best_d);
+        if (adm) {
+            Candidate c;
+            c.valid = 1;
+            c.cov = cov;
+            c.dist = dist;
+            c.i_base = i;
+            c.j_base = j;
+            c.i_slot = k;
+            c.j_slot = js;
+            if (cand_better(c, mine)) mine = c;
+        }
+    }
+    mine = block_best(mine, s_red);
+    if (threadIdx.x == 0) d.cand[g] = mine;
+}
+
+// After a scoring workgroup has written its candidate: the last of the
+// instance's scoring workgroups (device-scope counter) finishes the iteration.
+__device__ void finish_if_last(const InstDesc &d, Candidate *s_red, int32_t *s_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(d.counter, 1u);
+        const unsigned total = d.ngroups > 0 ? (unsigned)d.ngroups : 1u;
+        *s_flag = (prev + 1u == total);
+    }
+    __syncthreads();
+    if (*s_flag) {
+        __threadfence();
+        finish_iteration(d, s_red, s_flag);
+    }
+}
+
+template <int J, int U, bool NT>
+__device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jrow, int32_t m0,
+                                           int32_t m1, int32_t *t1c, int64_t *t1d, int32_t *bc,
+                                           u64 *bd)
+{
+    const int32_t K = d.K, R = d.R;
+    const v4i *b1v = reinterpret_cast<const v4i *>(d.b1);
+    const v4i *b2v = reinterpret_cast<const v4i *>(d.b2);
+    const v4i *o1v = reinterpret_cast<const v4i *>(d.o1);
+    const v4i *rows[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) rows[r] = reinterpret_cast<const v4i *>(d.C + (int64_t)jrow[r] * d.ldc);
+    const int32_t qend = m1 >> 2;
+    for (int32_t q0 = (m0 >> 2) + threadIdx.x; q0 < qend; q0 += U * kBlock) {
+        v4i cv[U][J], vb1[U], vb2[U], vo1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t q = q0 + u * kBlock;
+            if (q < qend) {
+#pragma unroll
+                for (int r = 0; r < J; ++r)
+                    cv[u][r] = NT ? __builtin_nontemporal_load(rows[r] + q) : rows[r][q];
+                vb1[u] = b1v[q];
+                vb2[u] = b2v[q];
+                vo1[u] = o1v[q];
+            } else {
+#pragma unroll
+                for (int r = 0; r < J; ++r) cv[u][r] = (v4i)(0);
+                vb1[u] = (v4i)(INT32_MIN);
+                vb2[u] = (v4i)(INT32_MIN);
+                vo1[u] = (v4i)(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t b1 = vb1[u][e], b2 = vb2[u][e], o1 = vo1[u][e];
+                const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
+                const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+#pragma unroll
+                for (int r = 0; r < J; ++r)
+                    visit(cv[u][r][e], b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c[r], t1d[r], bc + r * K,
+                          bd + r * K);
+            }
+        }
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *jrow, int32_t m0,
+                                             int32_t m1, int32_t *t1c, int64_t *t1d, int32_t *bc,
+                                             u64 *bd)
+{
+    const int32_t K = d.K, R = d.R;
+    const int32_t mend = min(m1, d.M);
+    const int64_t ldc = d.ldc;
+    for (int32_t m = m0 + threadIdx.x; m < mend; m += kBlock) {
+        int32_t cv[J];
+#pragma unroll
+        for (int r = 0; r < J; ++r) cv[r] = d.C[(int64_t)jrow[r] * ldc + m];
+        const int32_t b1 = d.b1[m], b2 = d.b2[m], o1 = d.o1[m];
+        const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
+        const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+#pragma unroll
+        for (int r = 0; r < J; ++r)
+            visit(cv[r], b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c[r], t1d[r], bc + r * K, bd + r * K);
+    }
+}
+
+// Workgroup reduction of the per-row common sums.
+template <int J>
+__device__ __forceinline__ void reduce_rows(const int32_t *t1c, const int64_t *t1d,
+                                            int32_t (*s_t1c)[J], int64_t (*s_t1d)[J],
+                                            int32_t *s_sum_c, int64_t *s_sum_d)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+        const int32_t c = wave_sum_i32(t1c[r]);
+        const int64_t dd = wave_sum_i64(t1d[r]);
+        if (lane == 0) {
+            s_t1c[wave][r] = c;
+            s_t1d[wave][r] = dd;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < J) {
+        int32_t c = 0;
+        int64_t dd = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            c += s_t1c[w][threadIdx.x];
+            dd += s_t1d[w][threadIdx.x];
+        }
+        s_sum_c[threadIdx.x] = c;
+        s_sum_d[threadIdx.x] = dd;
+    }
+    __syncthreads();
+}
+
+// One workgroup = J closed rows x one mission chunk of one instance.  Tiles
+// are ordered chunk-minor so that consecutive block ids (which the dispatcher
+// spreads over the XCDs) split an instance's mission axis and each XCD's L2
+// holds the b1/b2/o1 of fewer chunks.
+template <int J, int U, bool VEC4, bool NT>
+__global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ descs,
+                                                  const Tile *__restrict__ tiles, int fused)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const InstDesc &d = descs[tl.inst];
+    if (idle(d)) return;
+    const bool scoring = d.nsplit == 1;
+    if (d.st->stopped) {
+        if (scoring && fused && tl.g == 0 && threadIdx.x == 0) record_no_move(d);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t K = d.K;
+    const SweepLds L = carve_lds(smem, J, K);
+    __shared__ int32_t s_jrow[J];
+    __shared__ int32_t s_t1c[kBlock / 64][J];
+    __shared__ int64_t s_t1d[kBlock / 64][J];
+    __shared__ int32_t s_sum_c[J];
+    __shared__ int64_t s_sum_d[J];
+    __shared__ Candidate s_red[kBlock / 64 + 1];
+    __shared__ int32_t s_flag;
+
+    for (int q = threadIdx.x; q < J * K; q += kBlock) {
+        L.bd[q] = 0;
+        L.bc[q] = 0;
+    }
+    const int32_t nclosed = d.nclosed;
+    if (threadIdx.x < J) {
+        const int32_t js = tl.g * J + threadIdx.x;
+        s_jrow[threadIdx.x] = nclosed > 0 ? d.closed[js < nclosed ? js : 0] : 0;
+    }
+    __syncthreads();
+
+    int32_t jrow[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) jrow[r] = s_jrow[r];
+    int32_t t1c[J];
+    int64_t t1d[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+        t1c[r] = 0;
+        t1d[r] = 0;
+    }
+    if (nclosed > 0) {
+        const int32_t m0 = tl.sp * d.chunk;
+        const int32_t m1 = min(d.Mp, m0 + d.chunk);
+        if (VEC4)
+            sweep_vec4<J, U, NT>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+        else
+            sweep_scalar<J>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+    }
+    reduce_rows<J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
+
+    if (scoring) {
+        score_group(d, J, tl.g, s_jrow, L, s_sum_c, s_sum_d, s_red);
+        if (fused) finish_if_last(d, s_red, &s_flag);
+    } else {
+        // partial sums of this chunk: [T1, bin_0 .. bin_{K-1}] per row
+        const int32_t K1 = K + 1;
+        for (int32_t idx = threadIdx.x; idx < J * K1; idx += kBlock) {
+            const int32_t r = idx / K1, k = idx - r * K1;
+            const int32_t js = tl.g * J + r;
+            if (js >= nclosed) continue;
+            const int64_t at = ((int64_t)tl.sp * nclosed + js) * K1 + k;
+            if (k == 0) {
+                d.part_cov[at] = s_sum_c[r];
+                d.part_dist[at] = s_sum_d[r];
+            } else {
+                d.part_cov[at] = L.bc[r * K + k - 1];
+                d.part_dist[at] = (int64_t)L.bd[r * K + k - 1];
+            }
+        }
+    }
+}
+
+// Sums the chunk partials of one row group of a split instance and scores it.
+template <int J>
+__global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ descs,
+                                                  const Tile *__restrict__ tiles, int fused)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const InstDesc &d = descs[tl.inst];
+    if (idle(d)) return;
+    if (d.st->stopped) {
+        if (fused && tl.g == 0 && threadIdx.x == 0) record_no_move(d);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t K = d.K, K1 = K + 1;
+    const SweepLds L = carve_lds(smem, J, K);
+    __shared__ int32_t s_jrow[J];
+    __shared__ int32_t s_sum_c[J];
+    __shared__ int64_t s_sum_d[J];
+    __shared__ Candidate s_red[kBlock / 64 + 1];
+    __shared__ int32_t s_flag;
+    const int32_t nclosed = d.nclosed;
+    if (threadIdx.x < J) {
+        const int32_t js = tl.g * J + threadIdx.x;
+        s_jrow[threadIdx.x] = d.closed[js < nclosed ? js : 0];
+    }
+    for (int32_t idx = threadIdx.x; idx < J * K1; idx += kBlock) {
+        const int32_t r = idx / K1, k = idx - r * K1;
+        const int32_t js = tl.g * J + r;
+        int32_t c = 0;
+        int64_t dd = 0;
+        if (js < nclosed) {
+            for (int32_t sp = 0; sp < d.nsplit; ++sp) {
+                const int64_t at = ((int64_t)sp * nclosed + js) * K1 + k;
+                c += d.part_cov[at];
+                dd += d.part_dist[at];
+            }
+        }
+        if (k == 0) {
+            s_sum_c[r] = c;
+            s_sum_d[r] = dd;
+        } else {
+            L.bc[r * K + k - 1] = c;
+            L.bd[r * K + k - 1] = (u64)dd;
+        }
+    }
+    __syncthreads();
+    score_group(d, J, tl.g, s_jrow, L, s_sum_c, s_sum_d, s_red);
+    if (fused) finish_if_last(d, s_red, &s_flag);
+}
+
+// ---------------------------------------------------------------- assignment
+
+// Nearest open base of each mission (open ids ascending, so the first strict
+// minimum is the lowest id among equal costs), or -1 beyond R.
+__global__ __launch_bounds__(kBlock) void k_assign(const int32_t *__restrict__ C, int64_t ldc,
+                                                   int32_t M, const int32_t *__restrict__ open,
+                                                   int32_t K, int32_t R,
+                                                   int32_t *__restrict__ out)
+{
+    const int32_t m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= M) return;
+    int32_t v = INT32_MAX, who = -1;
+    for (int32_t k = 0; k < K; ++k) {
+        const int32_t id = open[k];
+        const int32_t c = C[(int64_t)id * ldc + m];
+        if (c < v) {
+            v = c;
+            who = id;
+        }
+    }
+    out[m] = v <= R ? who : -1;
+}
+
+// ---------------------------------------------------------------- batched ranking and outputs
+
+// Row sums of (instance, row) tiles with 4-byte loads (rows of any pitch).
+__global__ __launch_bounds__(kBlock) void k_rank_rows(const InstDesc *__restrict__ descs,
+                                                      const Tile *__restrict__ tiles)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const InstDesc &d = descs[tl.inst];
+    if (!d.active || !d.need_rank) return;
+    const int32_t *row = d.C + (int64_t)tl.g * d.ldc;
+    int64_t acc = 0;
+    for (int32_t m = threadIdx.x; m < d.M; m += kBlock) acc += row[m];
+    acc = wave_sum_i64(acc);
+    __shared__ int64_t part[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sum = 0;
+        for (int w = 0; w < kBlock / 64; ++w) sum += part[w];
+        d.sums[tl.g] = sum;
+    }
+}
+
+// One workgroup per instance: rank of every base by (sum, id); the K of rank
+// < K form the open list, the others the closed list, both in ascending id
+// order (the same lists the single-instance path builds on the host).  Sums
+// are compared from LDS tiles; positions come from a workgroup prefix count.
+__global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restrict__ descs)
+{
+    const InstDesc &d = descs[blockIdx.x];
+    if (!d.active || !d.need_rank) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *sel = smem;   // B flags
+    __shared__ int64_t tile[kBlock];
+    __shared__ int32_t s_cnt[kBlock];
+    const int32_t B = d.B, K = d.K;
+    for (int32_t b0 = 0; b0 < B; b0 += kBlock) {
+        const int32_t b = b0 + threadIdx.x;
+        const int64_t mine = b < B ? d.sums[b] : 0;
+        int32_t rank = 0;
+        for (int32_t t0 = 0; t0 < B; t0 += kBlock) {
+            __syncthreads();
+            if (t0 + (int32_t)threadIdx.x < B) tile[threadIdx.x] = d.sums[t0 + threadIdx.x];
+            __syncthreads();
+            const int32_t n = min(kBlock, B - t0);
+            for (int32_t q = 0; q < n; ++q) {
+                const int64_t o = tile[q];
+                rank += (o < mine) || (o == mine && t0 + q < b);
+            }
+        }
+        if (b < B) sel[b] = rank < K;
+    }
+    __syncthreads();
+    // each thread owns a contiguous run of ids; exclusive prefix of the counts
+    const int32_t per = (B + kBlock - 1) / kBlock;
+    const int32_t lo = min(B, (int32_t)threadIdx.x * per), hi = min(B, lo + per);
+    int32_t cnt = 0;
+    for (int32_t b = lo; b < hi; ++b) cnt += sel[b];
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < kBlock; ++w) {
+            const int32_t c = s_cnt[w];
+            s_cnt[w] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    int32_t before = s_cnt[threadIdx.x];
+    for (int32_t b = lo; b < hi; ++b) {
+        if (sel[b]) {
+            d.open[before] = b;
+            ++before;
+        } else {
+            d.closed[b - before] = b;
+        }
+    }
+}
+
+// One workgroup per instance: sorted best placement, mission assignment,
+// score and error flag.
+__global__ __launch_bounds__(kBlock) void k_outputs(const InstDesc *__restrict__ descs,
+                                                    fs_score *__restrict__ scores,
+                                                    int32_t *__restrict__ errors)
+{
+    const InstDesc &d = descs[blockIdx.x];
+    if (!d.active) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *sorted = reinterpret_cast<int32_t *>(smem);   // K
+    const int32_t K = d.K;
+    for (int32_t k = threadIdx.x; k < K; k += kBlock) {
+        const int32_t v = d.best_open[k];
+        int32_t pos = 0;
+        for (int32_t q = 0; q < K; ++q) pos += d.best_open[q] < v;
+        sorted[pos] = v;
+    }
+    __syncthreads();
+    if (d.best_out)
+        for (int32_t k = threadIdx.x; k < K; k += kBlock) d.best_out[k] = sorted[k];
+    if (d.assign_out) {
+        for (int32_t m = threadIdx.x; m < d.M; m += kBlock) {
+            int32_t v = INT32_MAX, who = -1;
+            for (int32_t k = 0; k < K; ++k) {
+                const int32_t id = sorted[k];
+                const int32_t c = d.C[(int64_t)id * d.ldc + m];
+                if (c < v) {
+                    v = c;
+                    who = id;
+                }
+            }
+            d.assign_out[m] = v <= d.R ? who : -1;
+        }
+    }
+    if (threadIdx.x == 0) {
+        fs_score sc;
+        sc.coverage = d.st->best_cov;
+        sc.best_iter = d.st->best_iter;
+        sc.distance = d.st->best_dist;
+        scores[blockIdx.x] = sc;
+        errors[blockIdx.x] = d.st->error ? d.st->err_iter : 0;
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <int J, int U, bool VEC4, bool NT>
+fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    const size_t lds = sweep_lds_bytes(J, c.Kmax);
+    if (t.nsweep > 0) {
+        k_sweep<J, U, VEC4, NT><<<t.nsweep, kBlock, lds, s>>>(t.desc, t.sweep, c.fused ? 1 : 0);
+        FS_HIP(hipGetLastError());
+    }
+    if (t.nscore > 0) {
+        k_score<J><<<t.nscore, kBlock, lds, s>>>(t.desc, t.score, c.fused ? 1 : 0);
+        FS_HIP(hipGetLastError());
+    }
+    return FS_OK;
+}
+
+template <int J, int U>
+fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    if (!c.vec4) return launch_sweep_t<J, 1, false, false>(t, c, s);
+    return c.nt ? launch_sweep_t<J, U, true, true>(t, c, s)
+                : launch_sweep_t<J, U, true, false>(t, c, s);
+}
+
+template <int J>
+fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    switch (c.U) {
+    case 1: return launch_sweep_ju<J, 1>(t, c, s);
+    case 2: return launch_sweep_ju<J, 2>(t, c, s);
+    case 4: return launch_sweep_ju<J, 4>(t, c, s);
+    default: return fail(FS_E_INTERNAL, "unsupported sweep unroll %d", c.U);
+    }
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- planning
+
+int choose_rows_per_group(int32_t nclosed, int32_t K)
+{
+    int J = 1;
+    if (nclosed >= 2048)
+        J = 4;
+    else if (nclosed >= 1024)
+        J = 2;
+    J = env_int("FS_SWEEP_J", J);
+    if (J != 1 && J != 2 && J != 4 && J != 8) J = 1;
+    while (J > 1 && sweep_lds_bytes(J, K) > 56 * 1024) J >>= 1;
+    return J;
+}
+
+int choose_unroll(int J)
+{
+    int U = J >= 8 ? 1 : (J >= 4 ? 2 : 4);
+    U = env_int("FS_SWEEP_U", U);
+    if (U != 1 && U != 2 && U != 4) U = 1;
+    return U;
+}
+
+InstPlan plan_instance(int32_t B, int32_t M, int32_t K, int J, int target_wg)
+{
+    InstPlan p;
+    const int32_t Mp = (M + 3) / 4 * 4;
+    p.nclosed = B - K;
+    p.ngroups = p.nclosed > 0 ? (p.nclosed + J - 1) / J : 0;
+    int nsplit = 1;
+    if (p.ngroups > 0 && target_wg > p.ngroups) {
+        nsplit = (target_wg + p.ngroups - 1) / p.ngroups;
+        nsplit = std::min(nsplit, std::max(1, Mp / 2048));
+    }
+    if (p.ngroups > 0) nsplit = env_int("FS_SWEEP_SPLIT", nsplit);
+    nsplit = std::max(1, std::min(nsplit, std::max(1, Mp / 4)));
+    if (p.ngroups == 0) nsplit = 1;
+    int chunk = (Mp + nsplit - 1) / nsplit;
+    chunk = (chunk + 3) / 4 * 4;
+    p.nsplit = (Mp + chunk - 1) / chunk;
+    p.chunk = chunk;
+    return p;
+}
+
+size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p, int32_t N_trace)
+{
+    (void)N_trace;
+    const size_t Mp = (size_t)(M + 3) / 4 * 4;
+    const size_t nclosed = (size_t)std::max(p.nclosed, 1);
+    size_t n = 0;
+    n += align_up(4 * (size_t)K, 256);                      // open
+    n += align_up(4 * nclosed, 256);                        // closed
+    n += align_up(4 * (size_t)B, 256);                      // tabu_until
+    n += 3 * align_up(4 * Mp, 256);                         // b1 b2 o1
+    n += align_up(sizeof(Acc) * kStripes * (K + 1), 256);   // accumulators
+    n += align_up(sizeof(Candidate) * std::max(p.ngroups, 1), 256);
+    n += align_up(sizeof(SolveState), 256);
+    n += align_up(4 * (size_t)K, 256);                      // best_open
+    n += 256;                                               // counter
+    if (p.nsplit > 1) {
+        const size_t np = (size_t)p.nsplit * p.nclosed * (K + 1);
+        n += align_up(4 * np, 256) + align_up(8 * np, 256);
+    }
+    return n;
+}
+
+void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, const InstPlan &p)
+{
+    const size_t Mp = (size_t)(M + 3) / 4 * 4;
+    const size_t nclosed = (size_t)std::max(p.nclosed, 1);
+    char *q = base;
+    auto take = [&](size_t bytes) {
+        char *r = q;
+        q += align_up(bytes, 256);
+        return r;
+    };
+    d.open = (int32_t *)take(4 * (size_t)K);
+    d.closed = (int32_t *)take(4 * nclosed);
+    d.tabu_until = (int32_t *)take(4 * (size_t)B);
+    d.b1 = (int32_t *)take(4 * Mp);
+    d.b2 = (int32_t *)take(4 * Mp);
+    d.o1 = (int32_t *)take(4 * Mp);
+    d.acc = (Acc *)take(sizeof(Acc) * kStripes * (K + 1));
+    d.cand = (Candidate *)take(sizeof(Candidate) * std::max(p.ngroups, 1));
+    d.st = (SolveState *)take(sizeof(SolveState));
+    d.best_open = (int32_t *)take(4 * (size_t)K);
+    d.counter = (unsigned int *)take(256);
+    d.part_cov = nullptr;
+    d.part_dist = nullptr;
+    if (p.nsplit > 1) {
+        const size_t np = (size_t)p.nsplit * p.nclosed * (K + 1);
+        d.part_cov = (int32_t *)take(4 * np);
+        d.part_dist = (int64_t *)take(8 * np);
+    }
+    d.B = B;
+    d.M = M;
+    d.Mp = (int32_t)Mp;
+    d.K = K;
+    d.nclosed = p.nclosed;
+    d.ngroups = p.ngroups;
+    d.nsplit = p.nsplit;
+    d.chunk = p.chunk;
+}
+
+void build_tiles(const std::vector<InstPlan> &plans, const std::vector<int32_t> &Mp,
+                 std::vector<Tile> &sweep, std::vector<Tile> &score, std::vector<Tile> &refresh)
+{
+    sweep.clear();
+    score.clear();
+    refresh.clear();
+    for (size_t i = 0; i < plans.size(); ++i) {
+        const InstPlan &p = plans[i];
+        const int32_t ng = std::max(p.ngroups, 1);
+        for (int32_t g = 0; g < ng; ++g)
+            for (int32_t sp = 0; sp < p.nsplit; ++sp) sweep.push_back(Tile{(int32_t)i, g, sp, 0});
+        if (p.nsplit > 1)
+            for (int32_t g = 0; g < p.ngroups; ++g) score.push_back(Tile{(int32_t)i, g, 0, 0});
+        const int32_t nt = (Mp[i] + kRefreshMissions - 1) / kRefreshMissions;
+        for (int32_t g = 0; g < nt; ++g) refresh.push_back(Tile{(int32_t)i, g, 0, 0});
+    }
+}
+
+// ---------------------------------------------------------------- launches
+
+fs_status engine_reset(const EngineTables &t, int32_t maxB, int32_t Kmax, hipStream_t s)
+{
+    const int32_t n = std::max(maxB, kStripes * (Kmax + 1));
+    const int per = (n + kBlock - 1) / kBlock;
+    k_reset<<<t.ninst * per, kBlock, 0, s>>>(t.desc, per);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    if (t.nrefresh == 0) return FS_OK;
+    TimedLaunch timed(1, s);
+    const size_t lds = 16 * (size_t)(c.Kmax + 1) + 4 * (size_t)c.Kmax;
+    k_refresh<<<t.nrefresh, kBlock, lds, s>>>(t.desc, t.refresh, 0);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_init_score(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    const size_t lds = 16 * (size_t)(c.Kmax + 1) + 4 * (size_t)c.Kmax;
+    if (t.nrefresh > 0) {
+        k_refresh<<<t.nrefresh, kBlock, lds, s>>>(t.desc, t.refresh, 1);
+        FS_HIP(hipGetLastError());
+    }
+    k_init_score<<<t.ninst, kBlock, 0, s>>>(t.desc);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    TimedLaunch timed(0, s);
+    switch (c.J) {
+    case 1: return launch_sweep_j<1>(t, c, s);
+    case 2: return launch_sweep_j<2>(t, c, s);
+    case 4: return launch_sweep_j<4>(t, c, s);
+    case 8: return launch_sweep_ju<8, 1>(t, c, s);
+    default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
+    }
+}
+
+fs_status engine_finalize(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    if (c.fused) return FS_OK;
+    TimedLaunch timed(2, s);
+    k_finalize<<<t.ninst, kBlock, 0, s>>>(t.desc);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nrow_tiles,
+                            int32_t Bmax, hipStream_t s)
+{
+    if (nrow_tiles > 0) {
+        k_rank_rows<<<nrow_tiles, kBlock, 0, s>>>(t.desc, row_tiles);
+        FS_HIP(hipGetLastError());
+    }
+    k_rank_lists<<<t.ninst, kBlock, (size_t)Bmax + 16, s>>>(t.desc);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_outputs(const EngineTables &t, int32_t Kmax, fs_score *scores, int32_t *errors,
+                         hipStream_t s)
+{
+    k_outputs<<<t.ninst, kBlock, 4 * (size_t)Kmax + 16, s>>>(t.desc, scores, errors);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_assign(const int32_t *C, int64_t ldc, int32_t M, const int32_t *open_sorted,
+                        int32_t K, int32_t R, int32_t *out, hipStream_t s)
+{
+    k_assign<<<(M + kBlock - 1) / kBlock, kBlock, 0, s>>>(C, ldc, M, open_sorted, K, R, out);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return FS_OK;
+    const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+    k_fill_i32<<<grid, kBlock, 0, s>>>(p, n, v);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s)
+{
+    if (n <= 0) return FS_OK;
+    const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+    k_fill_i64<<<grid, kBlock, 0, s>>>(p, n, v);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+}  // namespace fs

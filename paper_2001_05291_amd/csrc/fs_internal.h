@@ -97,58 +97,16 @@ struct Acc {
     unsigned long long dist;
 };
 
-// Device buffers of one single-instance solve.
-struct Workspace {
-    void *base = nullptr;
-    size_t bytes = 0;
-    int32_t *open = nullptr;        // K      slot -> base id
-    int32_t *closed = nullptr;      // B - K  slot -> base id
-    int32_t *tabu_until = nullptr;  // B
-    int32_t *b1 = nullptr;          // Mp     nearest open cost
-    int32_t *b2 = nullptr;          // Mp     second-nearest open cost
-    int32_t *o1 = nullptr;          // Mp     slot of the nearest open base
-    Acc *acc = nullptr;             // K + 1
-    Candidate *cand = nullptr;      // sweep workgroups
-    SolveState *st = nullptr;
-    int32_t *best_open = nullptr;   // K
-    int32_t *part_cov = nullptr;    // split partials: nsplit x nclosed x (K + 1)
-    int64_t *part_dist = nullptr;
-};
-
-// Launch geometry of the swap sweep.
-struct SweepPlan {
-    int J = 1;           // closed rows per workgroup
-    int nsplit = 1;      // mission chunks
-    int chunk = 0;       // missions per chunk (multiple of 4)
-    int ngroups = 0;     // row groups = ceil(nclosed / J)
-    int ncand = 0;       // candidates written per sweep
-    bool vec4 = true;    // 16-byte row loads
-};
-
-struct Problem {
-    const int32_t *C;
-    int64_t ldc;
-    int32_t B, M, K, R, T, N, mode;
-    int32_t Mp;          // M rounded up to a multiple of 4
-};
-
-SweepPlan plan_sweep(const Problem &pb);
-size_t workspace_bytes(const Problem &pb, const SweepPlan &plan);
-void carve_workspace(Workspace &ws, void *base, const Problem &pb, const SweepPlan &plan);
-
-// Stream-ordered launches (defined in tabu.hip).
-fs_status launch_setup(const Problem &pb, const SweepPlan &plan, const Workspace &ws,
-                       const int32_t *open_host, hipStream_t s);
-fs_status launch_refresh(const Problem &pb, const Workspace &ws, hipStream_t s);
-fs_status launch_init_score(const Problem &pb, const Workspace &ws, hipStream_t s);
-fs_status launch_sweep(const Problem &pb, const SweepPlan &plan, const Workspace &ws,
-                       int32_t *sc_cov, int64_t *sc_dist, hipStream_t s);
-fs_status launch_finalize(const Problem &pb, const SweepPlan &plan, const Workspace &ws,
-                          fs_trace_rec *trace, hipStream_t s);
-
 // Host-side validation helpers.
 fs_status check_table(const int32_t *C, int64_t ldc, int32_t B, int32_t M);
 fs_status check_open_list(const std::vector<int32_t> &ids, int32_t B);
+fs_status check_problem(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K, int32_t R);
+fs_status check_params(const fs_params *p);
+// Device-resident list of K ids -> host (synchronises the stream), validated.
+fs_status fetch_open_list(const int32_t *dev, int32_t K, int32_t B, std::vector<int32_t> &out,
+                          hipStream_t s);
+// Prefixes the current message with "<what> <index>: " and returns code.
+fs_status prefix_error(fs_status code, const char *what, int32_t index);
 
 // Base ranking on the device (rank.hip): row sums, then the K smallest
 // (sum, id) in rank order.

@@ -43,6 +43,15 @@ class Score(ctypes.Structure):
                 ("distance", ctypes.c_int64)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("B", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("K", ctypes.c_int32), ("range_m", ctypes.c_int32),
+                ("init_open", ctypes.c_void_p), ("best_open_out", ctypes.c_void_p),
+                ("assign_out", ctypes.c_void_p), ("trace_out", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(Instance) == 64
+
 _lib = None
 
 
@@ -69,6 +78,9 @@ def lib():
     L.fs_tabu_solve.restype = i32
     L.fs_tabu_solve.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(Params), vp, vp,
                                 ctypes.POINTER(Score), vp, vp, vp]
+    L.fs_tabu_solve_batch.restype = i32
+    L.fs_tabu_solve_batch.argtypes = [ctypes.POINTER(Instance), i32, ctypes.POINTER(Params),
+                                      ctypes.POINTER(Score), vp]
     L.fs_timing_enable.restype = i32
     L.fs_timing_enable.argtypes = [i32]
     L.fs_timing_read.restype = i32
@@ -184,6 +196,51 @@ def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int 
     if want_trace:
         tr = trace[: n * TRACE_DTYPE.itemsize].cpu().numpy().view(TRACE_DTYPE)
     return SolveResult(best, int(sc.coverage), int(sc.distance), int(sc.best_iter), assign, tr)
+
+
+def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
+                     want_assign: bool = True, want_trace: bool = True, stream=None):
+    """Solves many instances in one launch set.  Each item is a dict with keys
+    C (device int32 table), K, range_m, and optionally M and init_open.
+    Returns one SolveResult per instance (identical to tabu_solve alone)."""
+    n = len(instances)
+    arr = (Instance * n)()
+    keep = []
+    outs = []
+    nrec = max(int(iterations), 0)
+    for i, it in enumerate(instances):
+        C = it["C"]
+        B, M, ldc = _table(C, it.get("M"))
+        K = int(it["K"])
+        dev = C.device
+        best = torch.empty(K, dtype=torch.int32, device=dev)
+        assign = torch.empty(M, dtype=torch.int32, device=dev) if want_assign else None
+        trace = torch.empty(max(nrec, 1) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=dev) \
+            if want_trace else None
+        init = it.get("init_open")
+        if init is not None:
+            init = init.to(device=dev, dtype=torch.int32).contiguous()
+        keep += [C, init]
+        outs.append((best, assign, trace))
+        arr[i].C = C.data_ptr()
+        arr[i].ldc = ldc
+        arr[i].B, arr[i].M, arr[i].K = B, M, K
+        arr[i].range_m = int(it["range_m"])
+        arr[i].init_open = init.data_ptr() if init is not None else None
+        arr[i].best_open_out = best.data_ptr()
+        arr[i].assign_out = assign.data_ptr() if assign is not None else None
+        arr[i].trace_out = trace.data_ptr() if (trace is not None and nrec > 0) else None
+    p = Params(int(tenure), int(iterations), 0, int(mode))
+    scores = (Score * n)()
+    _check(lib().fs_tabu_solve_batch(arr, n, ctypes.byref(p), scores, _stream(stream)))
+    res = []
+    for i, (best, assign, trace) in enumerate(outs):
+        tr = None
+        if trace is not None:
+            tr = trace[: nrec * TRACE_DTYPE.itemsize].cpu().numpy().view(TRACE_DTYPE)
+        res.append(SolveResult(best, int(scores[i].coverage), int(scores[i].distance),
+                               int(scores[i].best_iter), assign, tr))
+    return res
 
 
 def timing_enable(on: bool = True) -> None:

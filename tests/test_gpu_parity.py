@@ -136,13 +136,14 @@ def test_move_scores_config1_and_2():
         check_scores(C, S.tolist(), c["R"])
 
 
-@pytest.mark.parametrize("J,split", [(1, 1), (2, 3), (4, 1), (8, 5), (1, 7)])
-def test_move_scores_launch_geometries(J, split):
+@pytest.mark.parametrize("J,split,U,nt", [(1, 1, 1, 1), (2, 3, 2, 0), (4, 1, 4, 1), (8, 5, 1, 1),
+                                          (1, 7, 4, 0), (2, 1, 4, 1), (4, 2, 2, 1)])
+def test_move_scores_launch_geometries(J, split, U, nt):
     inst = synth.make_instance(seed=31, B=90, H=200, M=4103)
     C = oracle_table(inst)
     rng = np.random.default_rng(J * 10 + split)
     S = rng.choice(90, 11, replace=False).tolist()
-    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
+    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt):
         check_scores(C, S, 1_000_000, ldc=4104)   # 16-byte rows
         check_scores(C, S, 1_000_000)             # 4-byte rows (ldc % 4 != 0)
 
@@ -233,6 +234,19 @@ def test_tabu_random_instances():
         assert_same_result(g, o, C, R)
 
 
+@pytest.mark.parametrize("fused", [0, 1])
+def test_local_search_stop_and_geometry(fused):
+    """Local search stops early; the remaining records are no-move records
+    whichever kernel writes them (fused finish, split scoring, standalone)."""
+    c = synth.CONFIGS[1]
+    _, C = instance_and_table(1)
+    for split in (1, 2):
+        with env(FS_FUSED_FINALIZE=fused, FS_SWEEP_SPLIT=split):
+            g, o = run_both(C, c["K"], c["R"], c["T"], 40, mode=1)
+        assert_same_result(g, o, C, c["R"])
+        assert g.trace["moved"][-1] == 0
+
+
 def test_special_cases():
     rng = np.random.default_rng(61)
     C = rng.integers(1, 100, size=(12, 50)).astype(np.int32)
@@ -258,8 +272,9 @@ def test_plans_are_bit_identical():
     _, C = instance_and_table(2)
     Cd = padded_table(C, c["M"])
     ref = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
-    for J, split in ((1, 1), (2, 4), (4, 9), (8, 2)):
-        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
+    for J, split, U, fused in ((1, 1, 1, 1), (2, 4, 2, 0), (4, 9, 4, 1), (8, 2, 1, 0),
+                               (4, 1, 2, 1), (1, 3, 4, 1)):
+        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_FUSED_FINALIZE=fused):
             g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
         assert np.array_equal(g.trace, ref.trace)
         assert np.array_equal(g.best_open.cpu().numpy(), ref.best_open.cpu().numpy())
