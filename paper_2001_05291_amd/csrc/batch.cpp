@@ -60,9 +60,9 @@ extern "C" fs_status fs_tabu_solve_batch(const fs_instance *inst, int32_t n, con
         sp.assign_out = q.assign_out;
     }
     // split an instance's missions only when the batch is too small to fill the GPU
-    const int target = std::max(0, env_int("FS_BATCH_TARGET_WG", 2048) / n);
+    const int target = std::max(0, env_int("FS_BATCH_TARGET_WG", 256) / n);
     LaunchSet ls;
-    FS_TRY(build_launch_set(specs, /*fused=*/true, target, ls, s));
+    FS_TRY(build_launch_set(specs, target, ls, s));
     FS_TRY(run_launch_set(ls, p->iterations, s));
     std::vector<fs_score> scores;
     std::vector<int32_t> errors;

@@ -17,18 +17,18 @@
 // adds the first sum to per-lane registers and the second to an LDS bin of
 // the out-slot o1(m).  One read of row j thus serves all K out-bases.
 //
-// Kernels of one iteration, each over a tile table spanning every instance of
-// the launch set:
-//   k_sweep    J closed rows x one mission chunk per workgroup; when an
-//              instance's missions are not split it also scores its J*K moves,
-//              keeps the best admissible one, and the last of the instance's
-//              workgroups to finish performs the argmax and applies the move
-//              (tabu list, best-so-far, trace);
-//   k_score    merges the chunk partials of split instances, then as above;
-//   k_refresh  nearest / second-nearest open cost of every mission, and the
-//              sums G and L_k, for the new placement.
-// All search state lives in device memory, so the host enqueues the same
-// launches every iteration.
+// One iteration is two kernels over tile tables that span every instance of
+// the launch set, with no device-wide synchronisation inside either:
+//   k_sweep    J closed rows x one mission chunk per workgroup; unsplit
+//              instances also score their J*K moves and store the row group's
+//              best admissible move (split instances go through k_score);
+//   k_refresh  every workgroup reduces the instance's row-group candidates to
+//              the chosen move (a few KB from L2, recomputed redundantly so no
+//              workgroup waits for another), applies it to its own copy of the
+//              open list and computes the nearest / second-nearest open cost
+//              of its 64 missions and their share of G and L_k; the
+//              workgroup of mission tile 0 also commits the move: lists for
+//              the next iteration, tabu list, best-so-far and trace.
 #include <algorithm>
 #include <cstdlib>
 
@@ -130,8 +130,6 @@ __device__ __forceinline__ void acc_sum(const Acc *acc, int32_t K, int32_t k, in
     dd = (int64_t)sd;
 }
 
-__device__ __forceinline__ bool idle(const InstDesc &d) { return !d.active || d.st->t >= d.N; }
-
 // ---------------------------------------------------------------- setup
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
@@ -148,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_i64(int64_t *p, int64_t n, int6
         p[q] = v;
 }
 
-// grid = ninst x per_inst blocks: tabu list, accumulators, state, counter.
+// grid = ninst x per_inst blocks: tabu list, both accumulators, state.
 __global__ __launch_bounds__(kBlock) void k_reset(const InstDesc *__restrict__ descs, int per_inst)
 {
     const int inst = blockIdx.x / per_inst, blk = blockIdx.x - inst * per_inst;
@@ -157,42 +155,212 @@ __global__ __launch_bounds__(kBlock) void k_reset(const InstDesc *__restrict__ d
     const int32_t q = blk * kBlock + threadIdx.x;
     if (q < d.B) d.tabu_until[q] = 0;
     if (q < kStripes * (d.K + 1)) {
-        d.acc[q].cov = 0;
-        d.acc[q].dist = 0;
+        d.acc[0][q].cov = 0;
+        d.acc[0][q].dist = 0;
+        d.acc[1][q].cov = 0;
+        d.acc[1][q].dist = 0;
     }
-    if (q == 0) {
-        *d.st = SolveState{};
-        *d.counter = 0u;
+    if (q == 0) *d.st = SolveState{};
+}
+
+// ---------------------------------------------------------------- ranking (A1)
+
+// Row sums of (instance, row) tiles with 4-byte loads (rows of any pitch).
+__global__ __launch_bounds__(kBlock) void k_rank_rows(const InstDesc *__restrict__ descs,
+                                                      const Tile *__restrict__ tiles)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const InstDesc &d = descs[tl.inst];
+    if (!d.active || !d.need_rank) return;
+    const int32_t *row = d.C + (int64_t)tl.g * d.ldc;
+    int64_t acc = 0;
+    for (int32_t m = threadIdx.x; m < d.M; m += kBlock) acc += row[m];
+    acc = wave_sum_i64(acc);
+    __shared__ int64_t part[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sum = 0;
+        for (int w = 0; w < kBlock / 64; ++w) sum += part[w];
+        d.sums[tl.g] = sum;
     }
 }
 
-// ---------------------------------------------------------------- refresh (A2)
+// One workgroup per instance: rank of every base by (sum, id); the K of rank
+// < K form the open list of S_1, the others its closed list, both in
+// ascending id order (the lists the single-instance path builds on the host).
+// Sums are compared from LDS tiles; positions come from a prefix count.
+__global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restrict__ descs)
+{
+    const InstDesc &d = descs[blockIdx.x];
+    if (!d.active || !d.need_rank) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *sel = smem;   // B flags
+    __shared__ int64_t tile[kBlock];
+    __shared__ int32_t s_cnt[kBlock];
+    const int32_t B = d.B, K = d.K;
+    for (int32_t b0 = 0; b0 < B; b0 += kBlock) {
+        const int32_t b = b0 + threadIdx.x;
+        const int64_t mine = b < B ? d.sums[b] : 0;
+        int32_t rank = 0;
+        for (int32_t t0 = 0; t0 < B; t0 += kBlock) {
+            __syncthreads();
+            if (t0 + (int32_t)threadIdx.x < B) tile[threadIdx.x] = d.sums[t0 + threadIdx.x];
+            __syncthreads();
+            const int32_t n = min(kBlock, B - t0);
+            for (int32_t q = 0; q < n; ++q) {
+                const int64_t o = tile[q];
+                rank += (o < mine) || (o == mine && t0 + q < b);
+            }
+        }
+        if (b < B) sel[b] = rank < K;
+    }
+    __syncthreads();
+    const int32_t per = (B + kBlock - 1) / kBlock;
+    const int32_t lo = min(B, (int32_t)threadIdx.x * per), hi = min(B, lo + per);
+    int32_t cnt = 0;
+    for (int32_t b = lo; b < hi; ++b) cnt += sel[b];
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < kBlock; ++w) {
+            const int32_t c = s_cnt[w];
+            s_cnt[w] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    int32_t before = s_cnt[threadIdx.x];
+    int32_t *op = d.open[1], *cl = d.closed[1];
+    for (int32_t b = lo; b < hi; ++b) {
+        if (sel[b]) {
+            op[before] = b;
+            ++before;
+        } else {
+            cl[b - before] = b;
+        }
+    }
+}
 
-// One workgroup = 64 missions (one per lane); the four waves split the open
-// slots (k = wave, wave + 4, ...), issue their loads together, and the partial
-// nearest / second-nearest are merged in LDS.  Ties in the nearest cost go to
-// the lower base id.  G and L_k are summed in LDS, then added with integer
-// atomics into one of kStripes accumulator copies (exact in any order).
+// ---------------------------------------------------------------- refresh (A2, A4, A5)
+
+// Trace record of iteration t; cur/best as they stand after it.
+__device__ void write_record(const InstDesc &d, int32_t t, const SolveState &s, int32_t moved,
+                             int32_t out_base, int32_t in_base)
+{
+    if (!d.trace) return;
+    fs_trace_rec rec;
+    rec.iter = t;
+    rec.out_base = moved ? out_base : -1;
+    rec.in_base = moved ? in_base : -1;
+    rec.moved = moved;
+    rec.cur_cov = s.cur_cov;
+    rec.best_cov = s.best_cov;
+    rec.cur_dist = s.cur_dist;
+    rec.best_dist = s.best_dist;
+    d.trace[t - 1] = rec;
+}
+
+// One workgroup = 64 missions of one instance (one per lane).
+//
+// After iteration t's sweep (t >= 1): the workgroup reduces the row-group
+// candidates to the chosen move, applies it to its LDS copy of the open list,
+// and computes the state of S_{t+1}.  The workgroup of mission tile 0 commits
+// the move.  With t == 0 it computes the state of S_1.
+//
+// State: the four waves split the open slots (k = wave, wave + 4, ...), issue
+// their loads together, and merge nearest / second-nearest in LDS; ties in the
+// nearest cost go to the lower base id.  G and L_k are summed in LDS, then
+// added with integer atomics into one of kStripes accumulator copies (exact in
+// any order).
 __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__ descs,
-                                                    const Tile *__restrict__ tiles, int initial)
+                                                    const Tile *__restrict__ tiles, int32_t step)
 {
     const Tile tl = tiles[blockIdx.x];
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
-    if (!initial && (d.st->stopped || d.st->t >= d.N)) return;
+    const int32_t t = step - d.start_step;
+    if (t < 0 || t > d.N) return;
     const int32_t K = d.K, M = d.M, R = d.R;
     const int64_t ldc = d.ldc;
+    SolveState *st = d.st;
+    const bool leader = tl.g == 0;
     extern __shared__ __align__(16) unsigned char smem[];
     u64 *s_cov = reinterpret_cast<u64 *>(smem);
     u64 *s_dist = s_cov + (K + 1);
     int32_t *s_open = reinterpret_cast<int32_t *>(s_dist + (K + 1));
     __shared__ int32_t p_v1[kBlock / 64][64], p_i1[kBlock / 64][64], p_s1[kBlock / 64][64],
         p_v2[kBlock / 64][64];
+    __shared__ Candidate s_red[kBlock / 64 + 1];
+    __shared__ int32_t s_improved;
+
+    if (t >= 1) {
+        if (st->stopped) {
+            // local search ended earlier: the iteration makes no move
+            if (leader && threadIdx.x == 0) write_record(d, t, *st, 0, -1, -1);
+            return;
+        }
+        const int32_t ncand = d.ngroups > 0 ? d.ngroups : 1;
+        Candidate best{};
+        for (int32_t q = threadIdx.x; q < ncand; q += kBlock) {
+            const Candidate c = d.cand[q];
+            if (cand_better(c, best)) best = c;
+        }
+        const int32_t *cur_open = d.open[t & 1];
+        for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = cur_open[k];
+        best = block_best(best, s_red);   // barriers: s_open complete too
+        if (!best.valid && d.mode == 1) {
+            // local optimum: stop; the placement and its state stay as they are
+            if (leader && threadIdx.x == 0) {
+                st->stopped = 1;
+                write_record(d, t, *st, 0, -1, -1);
+            }
+            return;
+        }
+        if (leader) {
+            // commit the move: next lists, tabu list, best-so-far, trace
+            if (threadIdx.x == 0) {
+                SolveState s = *st;
+                int32_t improved = 0;
+                if (best.valid) {
+                    d.tabu_until[best.i_base] = t + d.T;
+                    d.tabu_until[best.j_base] = t + d.T;
+                    s.cur_cov = best.cov;
+                    s.cur_dist = best.dist;
+                    if (better(best.cov, best.dist, s.best_cov, s.best_dist)) {
+                        s.best_cov = best.cov;
+                        s.best_dist = best.dist;
+                        s.best_iter = t;
+                        improved = 1;
+                    }
+                }
+                *st = s;
+                write_record(d, t, s, best.valid, best.i_base, best.j_base);
+                s_improved = improved;
+            }
+            __syncthreads();
+            int32_t *nxt_open = d.open[(t + 1) & 1];
+            int32_t *nxt_closed = d.closed[(t + 1) & 1];
+            const int32_t *cur_closed = d.closed[t & 1];
+            for (int k = threadIdx.x; k < K; k += kBlock) {
+                const int32_t v = (best.valid && k == best.i_slot) ? best.j_base : s_open[k];
+                nxt_open[k] = v;
+                if (s_improved) d.best_open[k] = v;
+            }
+            for (int32_t q = threadIdx.x; q < d.nclosed; q += kBlock)
+                nxt_closed[q] = (best.valid && q == best.j_slot) ? best.i_base : cur_closed[q];
+        }
+        __syncthreads();
+        if (best.valid && threadIdx.x == 0) s_open[best.i_slot] = best.j_base;
+    } else {
+        const int32_t *first = d.open[1];
+        for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = first[k];
+    }
     for (int k = threadIdx.x; k <= K; k += kBlock) {
         s_cov[k] = 0;
         s_dist[k] = 0;
     }
-    for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = d.open[k];
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -275,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         }
     }
     __syncthreads();
-    Acc *acc = d.acc + (blockIdx.x & (kStripes - 1)) * (K + 1);
+    Acc *acc = d.acc[(t + 1) & 1] + (blockIdx.x & (kStripes - 1)) * (K + 1);
     for (int k = threadIdx.x; k <= K; k += kBlock) {
         const u64 c = s_cov[k], dd = s_dist[k];
         if (c | dd) {
@@ -285,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     }
 }
 
-// cur = best = G of the initial placement; best_open = open.  grid = ninst.
+// cur = best = G of S_1; best_open = its open list.  grid = ninst.
 __global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restrict__ descs)
 {
     const InstDesc &d = descs[blockIdx.x];
@@ -293,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restric
     if (threadIdx.x == 0) {
         int32_t gc;
         int64_t gd;
-        acc_sum(d.acc, d.K, 0, gc, gd);
+        acc_sum(d.acc[1], d.K, 0, gc, gd);
         SolveState s{};
         s.cur_cov = gc;
         s.cur_dist = gd;
@@ -301,110 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restric
         s.best_dist = gd;
         *d.st = s;
     }
-    for (int k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[k];
-}
-
-// ---------------------------------------------------------------- finish (A4 global, A5)
-
-// Trace record of an iteration without a move (local search already stopped).
-__device__ void record_no_move(const InstDesc &d)
-{
-    SolveState *st = d.st;
-    const int32_t t = st->t + 1;
-    if (d.trace) {
-        fs_trace_rec rec;
-        rec.iter = t;
-        rec.out_base = -1;
-        rec.in_base = -1;
-        rec.moved = 0;
-        rec.cur_cov = st->cur_cov;
-        rec.best_cov = st->best_cov;
-        rec.cur_dist = st->cur_dist;
-        rec.best_dist = st->best_dist;
-        d.trace[t - 1] = rec;
-    }
-    st->t = t;
-}
-
-// One workgroup: argmax over the instance's candidates, then apply the move,
-// update the tabu list, the best-so-far and the trace, and clear the
-// accumulators and the counter for the next iteration.
-__device__ void finish_iteration(const InstDesc &d, Candidate *s_red, int32_t *s_flag)
-{
-    SolveState *st = d.st;
-    const int32_t ncand = d.ngroups > 0 ? d.ngroups : 1;
-    Candidate best{};
-    for (int32_t q = threadIdx.x; q < ncand; q += kBlock) {
-        const Candidate c = d.cand[q];
-        if (cand_better(c, best)) best = c;
-    }
-    best = block_best(best, s_red);
-    if (threadIdx.x == 0) {
-        const int32_t t = st->t + 1;
-        int32_t moved = 0, improved = 0;
-        // the refreshed value of the current placement must equal the score
-        // the previous move was chosen with
-        int32_t gc;
-        int64_t gd;
-        acc_sum(d.acc, d.K, 0, gc, gd);
-        if ((gc != st->cur_cov || gd != st->cur_dist) && !st->error) {
-            st->error = 1;
-            st->err_iter = t;
-        }
-        if (best.valid) {
-            d.open[best.i_slot] = best.j_base;
-            d.closed[best.j_slot] = best.i_base;
-            d.tabu_until[best.i_base] = t + d.T;
-            d.tabu_until[best.j_base] = t + d.T;
-            st->cur_cov = best.cov;
-            st->cur_dist = best.dist;
-            moved = 1;
-            if (better(best.cov, best.dist, st->best_cov, st->best_dist)) {
-                st->best_cov = best.cov;
-                st->best_dist = best.dist;
-                st->best_iter = t;
-                improved = 1;
-            }
-        } else if (d.mode == 1) {
-            st->stopped = 1;
-        }
-        if (d.trace) {
-            fs_trace_rec rec;
-            rec.iter = t;
-            rec.out_base = moved ? best.i_base : -1;
-            rec.in_base = moved ? best.j_base : -1;
-            rec.moved = moved;
-            rec.cur_cov = st->cur_cov;
-            rec.best_cov = st->best_cov;
-            rec.cur_dist = st->cur_dist;
-            rec.best_dist = st->best_dist;
-            d.trace[t - 1] = rec;
-        }
-        st->t = t;
-        *s_flag = improved;
-    }
-    __syncthreads();
-    if (*s_flag)
-        for (int32_t k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[k];
-    for (int32_t q = threadIdx.x; q < kStripes * (d.K + 1); q += kBlock) {
-        d.acc[q].cov = 0;
-        d.acc[q].dist = 0;
-    }
-    if (threadIdx.x == 0) *d.counter = 0u;
-}
-
-// Standalone finish (grid = ninst): instances without fused finishing.
-__global__ __launch_bounds__(kBlock) void k_finalize(const InstDesc *__restrict__ descs)
-{
-    __shared__ Candidate s_red[kBlock / 64 + 1];
-    __shared__ int32_t s_flag;
-    const InstDesc &d = descs[blockIdx.x];
-    if (idle(d)) return;
-    if (d.st->stopped) {
-        if (threadIdx.x == 0) record_no_move(d);
-        return;
-    }
-    finish_iteration(d, s_red, &s_flag);
+    for (int k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[1][k];
 }
 
 // ---------------------------------------------------------------- sweep (A3, A4 local)
@@ -433,15 +498,16 @@ __device__ __forceinline__ void visit(int32_t c, int32_t b1, int32_t b2, int32_t
 // LDS of the sweep / score kernels for J rows and up to Kmax slots.
 __host__ __device__ constexpr size_t sweep_lds_bytes(int J, int Kmax)
 {
-    return (size_t)J * Kmax * 12 + (size_t)(Kmax + 1) * 12 + (size_t)Kmax * 4 + 16;
+    return (size_t)J * Kmax * 12 + (size_t)(Kmax + 1) * 12 + (size_t)Kmax * 8 + 16;
 }
 
 struct SweepLds {
-    u64 *bd;       // J*K bins: distance
-    int64_t *Ld;   // K+1: G, L_k distance
-    int32_t *bc;   // J*K bins: coverage
-    int32_t *Lc;   // K+1: G, L_k coverage
-    int32_t *open; // K
+    u64 *bd;        // J*K bins: distance
+    int64_t *Ld;    // K+1: G, L_k distance
+    int32_t *bc;    // J*K bins: coverage
+    int32_t *Lc;    // K+1: G, L_k coverage
+    int32_t *open;  // K: open base of each slot
+    int32_t *otabu; // K: tabu_until of each open base
 };
 
 __device__ __forceinline__ SweepLds carve_lds(unsigned char *smem, int J, int K)
@@ -452,28 +518,41 @@ __device__ __forceinline__ SweepLds carve_lds(unsigned char *smem, int J, int K)
     s.bc = reinterpret_cast<int32_t *>(s.Ld + (K + 1));
     s.Lc = s.bc + J * K;
     s.open = s.Lc + (K + 1);
+    s.otabu = s.open + K;
     return s;
+}
+
+// Per-slot inputs of the scoring step, loaded before the streaming loop so
+// their latency overlaps it: G and L_k (summed over the stripes), the open
+// list and the tabu state of the open bases.
+__device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, const SweepLds &L)
+{
+    const int32_t K = d.K;
+    const Acc *acc = d.acc[t & 1];
+    const int32_t *op = d.open[t & 1];
+    for (int32_t k = threadIdx.x; k <= K; k += kBlock) {
+        int32_t c;
+        int64_t dd;
+        acc_sum(acc, K, k, c, dd);
+        L.Lc[k] = c;
+        L.Ld[k] = dd;
+        if (k < K) {
+            const int32_t id = op[k];
+            L.open[k] = id;
+            L.otabu[k] = d.tabu_until[id];
+        }
+    }
 }
 
 // Scores of the J x K moves of row group g from the per-row common sums
 // (t1c, t1d) and the per-(row, out-slot) bins; writes the optional full score
 // table and the group's best admissible candidate.
-__device__ void score_group(const InstDesc &d, int J, int32_t g, const int32_t *s_jrow,
-                            const SweepLds &L, const int32_t *t1c, const int64_t *t1d,
-                            Candidate *s_red)
+__device__ void score_group(const InstDesc &d, int J, int32_t t, int32_t g,
+                            const int32_t *s_jrow, const int32_t *s_jtabu, const SweepLds &L,
+                            const int32_t *t1c, const int64_t *t1d, Candidate *s_red)
 {
     const int32_t K = d.K;
-    for (int32_t k = threadIdx.x; k <= K; k += kBlock) {
-        int32_t c;
-        int64_t dd;
-        acc_sum(d.acc, K, k, c, dd);
-        L.Lc[k] = c;
-        L.Ld[k] = dd;
-    }
-    for (int32_t k = threadIdx.x; k < K; k += kBlock) L.open[k] = d.open[k];
-    __syncthreads();
     const SolveState *st = d.st;
-    const int32_t t = st->t + 1;
     const int32_t cur_c = st->cur_cov, best_c = st->best_cov;
     const int64_t cur_d = st->cur_dist, best_d = st->best_dist;
     const int32_t Gc = L.Lc[0];
@@ -494,7 +573,7 @@ __device__ void score_group(const InstDesc &d, int J, int32_t g, const int32_t *
         if (d.mode == 1)
             adm = better(cov, dist, cur_c, cur_d);
         else
-            adm = (d.tabu_until[i] < t && d.tabu_until[j] < t) || better(cov, dist, best_c, best_d);
+            adm = (L.otabu[k] < t && s_jtabu[r] < t) || better(cov, dist, best_c, best_d);
         if (adm) {
             Candidate c;
             c.valid = 1;
@@ -509,24 +588,6 @@ __device__ void score_group(const InstDesc &d, int J, int32_t g, const int32_t *
     }
     mine = block_best(mine, s_red);
     if (threadIdx.x == 0) d.cand[g] = mine;
-}
-
-// After a scoring workgroup has written its candidate: the last of the
-// instance's scoring workgroups (device-scope counter) finishes the iteration.
-__device__ void finish_if_last(const InstDesc &d, Candidate *s_red, int32_t *s_flag)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(d.counter, 1u);
-        const unsigned total = d.ngroups > 0 ? (unsigned)d.ngroups : 1u;
-        *s_flag = (prev + 1u == total);
-    }
-    __syncthreads();
-    if (*s_flag) {
-        __threadfence();
-        finish_iteration(d, s_red, s_flag);
-    }
 }
 
 template <int J, int U, bool NT>
@@ -629,33 +690,53 @@ __device__ __forceinline__ void reduce_rows(const int32_t *t1c, const int64_t *t
     __syncthreads();
 }
 
+// The work of an instance's first sweep workgroup besides its tile: clear the
+// accumulators the coming refresh fills, and check that the value of S_t
+// recounted by the previous refresh equals the score its move was chosen with.
+__device__ void sweep_housekeeping(const InstDesc &d, int32_t t)
+{
+    Acc *nxt = d.acc[(t + 1) & 1];
+    for (int32_t q = threadIdx.x; q < kStripes * (d.K + 1); q += kBlock) {
+        nxt[q].cov = 0;
+        nxt[q].dist = 0;
+    }
+    if (threadIdx.x == 0) {
+        int32_t gc;
+        int64_t gd;
+        acc_sum(d.acc[t & 1], d.K, 0, gc, gd);
+        SolveState *st = d.st;
+        if ((gc != st->cur_cov || gd != st->cur_dist) && !st->error) {
+            st->error = 1;
+            st->err_iter = t;
+        }
+    }
+}
+
 // One workgroup = J closed rows x one mission chunk of one instance.  Tiles
 // are ordered chunk-minor so that consecutive block ids (which the dispatcher
 // spreads over the XCDs) split an instance's mission axis and each XCD's L2
 // holds the b1/b2/o1 of fewer chunks.
 template <int J, int U, bool VEC4, bool NT>
 __global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ descs,
-                                                  const Tile *__restrict__ tiles, int fused)
+                                                  const Tile *__restrict__ tiles, int32_t step)
 {
     const Tile tl = tiles[blockIdx.x];
     const InstDesc &d = descs[tl.inst];
-    if (idle(d)) return;
+    if (!d.active) return;
+    const int32_t t = step - d.start_step;
+    if (t < 1 || t > d.N || d.st->stopped) return;
     const bool scoring = d.nsplit == 1;
-    if (d.st->stopped) {
-        if (scoring && fused && tl.g == 0 && threadIdx.x == 0) record_no_move(d);
-        return;
-    }
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K;
     const SweepLds L = carve_lds(smem, J, K);
-    __shared__ int32_t s_jrow[J];
+    __shared__ int32_t s_jrow[J], s_jtabu[J];
     __shared__ int32_t s_t1c[kBlock / 64][J];
     __shared__ int64_t s_t1d[kBlock / 64][J];
     __shared__ int32_t s_sum_c[J];
     __shared__ int64_t s_sum_d[J];
     __shared__ Candidate s_red[kBlock / 64 + 1];
-    __shared__ int32_t s_flag;
 
+    if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
     for (int q = threadIdx.x; q < J * K; q += kBlock) {
         L.bd[q] = 0;
         L.bc[q] = 0;
@@ -663,8 +744,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ d
     const int32_t nclosed = d.nclosed;
     if (threadIdx.x < J) {
         const int32_t js = tl.g * J + threadIdx.x;
-        s_jrow[threadIdx.x] = nclosed > 0 ? d.closed[js < nclosed ? js : 0] : 0;
+        const int32_t j = nclosed > 0 ? d.closed[t & 1][js < nclosed ? js : 0] : 0;
+        s_jrow[threadIdx.x] = j;
+        if (scoring) s_jtabu[threadIdx.x] = d.tabu_until[j];
     }
+    if (scoring) load_slot_inputs(d, t, L);
     __syncthreads();
 
     int32_t jrow[J];
@@ -688,8 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ d
     reduce_rows<J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
 
     if (scoring) {
-        score_group(d, J, tl.g, s_jrow, L, s_sum_c, s_sum_d, s_red);
-        if (fused) finish_if_last(d, s_red, &s_flag);
+        score_group(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
     } else {
         // partial sums of this chunk: [T1, bin_0 .. bin_{K-1}] per row
         const int32_t K1 = K + 1;
@@ -712,28 +795,28 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ d
 // Sums the chunk partials of one row group of a split instance and scores it.
 template <int J>
 __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ descs,
-                                                  const Tile *__restrict__ tiles, int fused)
+                                                  const Tile *__restrict__ tiles, int32_t step)
 {
     const Tile tl = tiles[blockIdx.x];
     const InstDesc &d = descs[tl.inst];
-    if (idle(d)) return;
-    if (d.st->stopped) {
-        if (fused && tl.g == 0 && threadIdx.x == 0) record_no_move(d);
-        return;
-    }
+    if (!d.active) return;
+    const int32_t t = step - d.start_step;
+    if (t < 1 || t > d.N || d.st->stopped) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K, K1 = K + 1;
     const SweepLds L = carve_lds(smem, J, K);
-    __shared__ int32_t s_jrow[J];
+    __shared__ int32_t s_jrow[J], s_jtabu[J];
     __shared__ int32_t s_sum_c[J];
     __shared__ int64_t s_sum_d[J];
     __shared__ Candidate s_red[kBlock / 64 + 1];
-    __shared__ int32_t s_flag;
     const int32_t nclosed = d.nclosed;
     if (threadIdx.x < J) {
         const int32_t js = tl.g * J + threadIdx.x;
-        s_jrow[threadIdx.x] = d.closed[js < nclosed ? js : 0];
+        const int32_t j = d.closed[t & 1][js < nclosed ? js : 0];
+        s_jrow[threadIdx.x] = j;
+        s_jtabu[threadIdx.x] = d.tabu_until[j];
     }
+    load_slot_inputs(d, t, L);
     for (int32_t idx = threadIdx.x; idx < J * K1; idx += kBlock) {
         const int32_t r = idx / K1, k = idx - r * K1;
         const int32_t js = tl.g * J + r;
@@ -755,194 +838,110 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
         }
     }
     __syncthreads();
-    score_group(d, J, tl.g, s_jrow, L, s_sum_c, s_sum_d, s_red);
-    if (fused) finish_if_last(d, s_red, &s_flag);
+    score_group(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
 }
 
-// ---------------------------------------------------------------- assignment
+// ---------------------------------------------------------------- outputs
 
-// Nearest open base of each mission (open ids ascending, so the first strict
-// minimum is the lowest id among equal costs), or -1 beyond R.
-__global__ __launch_bounds__(kBlock) void k_assign(const int32_t *__restrict__ C, int64_t ldc,
-                                                   int32_t M, const int32_t *__restrict__ open,
-                                                   int32_t K, int32_t R,
-                                                   int32_t *__restrict__ out)
-{
-    const int32_t m = blockIdx.x * kBlock + threadIdx.x;
-    if (m >= M) return;
-    int32_t v = INT32_MAX, who = -1;
-    for (int32_t k = 0; k < K; ++k) {
-        const int32_t id = open[k];
-        const int32_t c = C[(int64_t)id * ldc + m];
-        if (c < v) {
-            v = c;
-            who = id;
-        }
-    }
-    out[m] = v <= R ? who : -1;
-}
-
-// ---------------------------------------------------------------- batched ranking and outputs
-
-// Row sums of (instance, row) tiles with 4-byte loads (rows of any pitch).
-__global__ __launch_bounds__(kBlock) void k_rank_rows(const InstDesc *__restrict__ descs,
-                                                      const Tile *__restrict__ tiles)
-{
-    const Tile tl = tiles[blockIdx.x];
-    const InstDesc &d = descs[tl.inst];
-    if (!d.active || !d.need_rank) return;
-    const int32_t *row = d.C + (int64_t)tl.g * d.ldc;
-    int64_t acc = 0;
-    for (int32_t m = threadIdx.x; m < d.M; m += kBlock) acc += row[m];
-    acc = wave_sum_i64(acc);
-    __shared__ int64_t part[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t sum = 0;
-        for (int w = 0; w < kBlock / 64; ++w) sum += part[w];
-        d.sums[tl.g] = sum;
-    }
-}
-
-// One workgroup per instance: rank of every base by (sum, id); the K of rank
-// < K form the open list, the others the closed list, both in ascending id
-// order (the same lists the single-instance path builds on the host).  Sums
-// are compared from LDS tiles; positions come from a workgroup prefix count.
-__global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restrict__ descs)
-{
-    const InstDesc &d = descs[blockIdx.x];
-    if (!d.active || !d.need_rank) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    unsigned char *sel = smem;   // B flags
-    __shared__ int64_t tile[kBlock];
-    __shared__ int32_t s_cnt[kBlock];
-    const int32_t B = d.B, K = d.K;
-    for (int32_t b0 = 0; b0 < B; b0 += kBlock) {
-        const int32_t b = b0 + threadIdx.x;
-        const int64_t mine = b < B ? d.sums[b] : 0;
-        int32_t rank = 0;
-        for (int32_t t0 = 0; t0 < B; t0 += kBlock) {
-            __syncthreads();
-            if (t0 + (int32_t)threadIdx.x < B) tile[threadIdx.x] = d.sums[t0 + threadIdx.x];
-            __syncthreads();
-            const int32_t n = min(kBlock, B - t0);
-            for (int32_t q = 0; q < n; ++q) {
-                const int64_t o = tile[q];
-                rank += (o < mine) || (o == mine && t0 + q < b);
-            }
-        }
-        if (b < B) sel[b] = rank < K;
-    }
-    __syncthreads();
-    // each thread owns a contiguous run of ids; exclusive prefix of the counts
-    const int32_t per = (B + kBlock - 1) / kBlock;
-    const int32_t lo = min(B, (int32_t)threadIdx.x * per), hi = min(B, lo + per);
-    int32_t cnt = 0;
-    for (int32_t b = lo; b < hi; ++b) cnt += sel[b];
-    s_cnt[threadIdx.x] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int w = 0; w < kBlock; ++w) {
-            const int32_t c = s_cnt[w];
-            s_cnt[w] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-    int32_t before = s_cnt[threadIdx.x];
-    for (int32_t b = lo; b < hi; ++b) {
-        if (sel[b]) {
-            d.open[before] = b;
-            ++before;
-        } else {
-            d.closed[b - before] = b;
-        }
-    }
-}
-
-// One workgroup per instance: sorted best placement, mission assignment,
-// score and error flag.
+// One workgroup per instance: best placement in ascending id order, score,
+// and the first iteration whose refreshed value disagreed with its score.
 __global__ __launch_bounds__(kBlock) void k_outputs(const InstDesc *__restrict__ descs,
                                                     fs_score *__restrict__ scores,
                                                     int32_t *__restrict__ errors)
 {
     const InstDesc &d = descs[blockIdx.x];
     if (!d.active) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    int32_t *sorted = reinterpret_cast<int32_t *>(smem);   // K
     const int32_t K = d.K;
     for (int32_t k = threadIdx.x; k < K; k += kBlock) {
         const int32_t v = d.best_open[k];
         int32_t pos = 0;
         for (int32_t q = 0; q < K; ++q) pos += d.best_open[q] < v;
-        sorted[pos] = v;
-    }
-    __syncthreads();
-    if (d.best_out)
-        for (int32_t k = threadIdx.x; k < K; k += kBlock) d.best_out[k] = sorted[k];
-    if (d.assign_out) {
-        for (int32_t m = threadIdx.x; m < d.M; m += kBlock) {
-            int32_t v = INT32_MAX, who = -1;
-            for (int32_t k = 0; k < K; ++k) {
-                const int32_t id = sorted[k];
-                const int32_t c = d.C[(int64_t)id * d.ldc + m];
-                if (c < v) {
-                    v = c;
-                    who = id;
-                }
-            }
-            d.assign_out[m] = v <= d.R ? who : -1;
-        }
+        d.best_sorted[pos] = v;
+        if (d.best_out) d.best_out[pos] = v;
     }
     if (threadIdx.x == 0) {
+        const SolveState *st = d.st;
         fs_score sc;
-        sc.coverage = d.st->best_cov;
-        sc.best_iter = d.st->best_iter;
-        sc.distance = d.st->best_dist;
+        sc.coverage = st->best_cov;
+        sc.best_iter = st->best_iter;
+        sc.distance = st->best_dist;
         scores[blockIdx.x] = sc;
-        errors[blockIdx.x] = d.st->error ? d.st->err_iter : 0;
+        int32_t err = st->error ? st->err_iter : 0;
+        // the state after the last move was refreshed too: check it
+        if (!err && d.N >= 1 && !st->stopped) {
+            int32_t gc;
+            int64_t gd;
+            acc_sum(d.acc[(d.N + 1) & 1], K, 0, gc, gd);
+            if (gc != st->cur_cov || gd != st->cur_dist) err = d.N + 1;
+        }
+        errors[blockIdx.x] = err;
     }
+}
+
+// Nearest open base of each mission of the best placement (ascending ids, so
+// the first strict minimum is the lowest id among equal costs), or -1 beyond
+// R.  Tiles of 64 missions (the refresh tiles); one mission per thread of the
+// first wave.
+__global__ __launch_bounds__(kBlock) void k_assign(const InstDesc *__restrict__ descs,
+                                                   const Tile *__restrict__ tiles)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const InstDesc &d = descs[tl.inst];
+    if (!d.active || !d.assign_out) return;
+    if (threadIdx.x >= kRefreshMissions) return;
+    const int32_t m = tl.g * kRefreshMissions + threadIdx.x;
+    if (m >= d.M) return;
+    int32_t v = INT32_MAX, who = -1;
+    for (int32_t k = 0; k < d.K; ++k) {
+        const int32_t id = d.best_sorted[k];
+        const int32_t c = d.C[(int64_t)id * d.ldc + m];
+        if (c < v) {
+            v = c;
+            who = id;
+        }
+    }
+    d.assign_out[m] = v <= d.R ? who : -1;
 }
 
 // ---------------------------------------------------------------- dispatch
 
 template <int J, int U, bool VEC4, bool NT>
-fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
     const size_t lds = sweep_lds_bytes(J, c.Kmax);
     if (t.nsweep > 0) {
-        k_sweep<J, U, VEC4, NT><<<t.nsweep, kBlock, lds, s>>>(t.desc, t.sweep, c.fused ? 1 : 0);
+        k_sweep<J, U, VEC4, NT><<<t.nsweep, kBlock, lds, s>>>(t.desc, t.sweep, step);
         FS_HIP(hipGetLastError());
     }
     if (t.nscore > 0) {
-        k_score<J><<<t.nscore, kBlock, lds, s>>>(t.desc, t.score, c.fused ? 1 : 0);
+        k_score<J><<<t.nscore, kBlock, lds, s>>>(t.desc, t.score, step);
         FS_HIP(hipGetLastError());
     }
     return FS_OK;
 }
 
 template <int J, int U>
-fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
-    if (!c.vec4) return launch_sweep_t<J, 1, false, false>(t, c, s);
-    return c.nt ? launch_sweep_t<J, U, true, true>(t, c, s)
-                : launch_sweep_t<J, U, true, false>(t, c, s);
+    if (!c.vec4) return launch_sweep_t<J, 1, false, false>(t, c, step, s);
+    return c.nt ? launch_sweep_t<J, U, true, true>(t, c, step, s)
+                : launch_sweep_t<J, U, true, false>(t, c, step, s);
 }
 
 template <int J>
-fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
     switch (c.U) {
-    case 1: return launch_sweep_ju<J, 1>(t, c, s);
-    case 2: return launch_sweep_ju<J, 2>(t, c, s);
-    case 4: return launch_sweep_ju<J, 4>(t, c, s);
+    case 1: return launch_sweep_ju<J, 1>(t, c, step, s);
+    case 2: return launch_sweep_ju<J, 2>(t, c, step, s);
+    case 4: return launch_sweep_ju<J, 4>(t, c, step, s);
     default: return fail(FS_E_INTERNAL, "unsupported sweep unroll %d", c.U);
     }
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t refresh_lds_bytes(int Kmax) { return 16 * (size_t)(Kmax + 1) + 4 * (size_t)Kmax + 16; }
 
 }  // namespace
 
@@ -963,7 +962,7 @@ int choose_rows_per_group(int32_t nclosed, int32_t K)
 
 int choose_unroll(int J)
 {
-    int U = J >= 8 ? 1 : (J >= 4 ? 2 : 4);
+    int U = J >= 4 ? 1 : (J >= 2 ? 2 : 4);
     U = env_int("FS_SWEEP_U", U);
     if (U != 1 && U != 2 && U != 4) U = 1;
     return U;
@@ -990,21 +989,19 @@ InstPlan plan_instance(int32_t B, int32_t M, int32_t K, int J, int target_wg)
     return p;
 }
 
-size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p, int32_t N_trace)
+size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
 {
-    (void)N_trace;
     const size_t Mp = (size_t)(M + 3) / 4 * 4;
     const size_t nclosed = (size_t)std::max(p.nclosed, 1);
     size_t n = 0;
-    n += align_up(4 * (size_t)K, 256);                      // open
-    n += align_up(4 * nclosed, 256);                        // closed
-    n += align_up(4 * (size_t)B, 256);                      // tabu_until
-    n += 3 * align_up(4 * Mp, 256);                         // b1 b2 o1
-    n += align_up(sizeof(Acc) * kStripes * (K + 1), 256);   // accumulators
+    n += 2 * align_up(4 * (size_t)K, 256);                      // open lists
+    n += 2 * align_up(4 * nclosed, 256);                        // closed lists
+    n += align_up(4 * (size_t)B, 256);                          // tabu_until
+    n += 3 * align_up(4 * Mp, 256);                             // b1 b2 o1
+    n += 2 * align_up(sizeof(Acc) * kStripes * (K + 1), 256);   // accumulators
     n += align_up(sizeof(Candidate) * std::max(p.ngroups, 1), 256);
     n += align_up(sizeof(SolveState), 256);
-    n += align_up(4 * (size_t)K, 256);                      // best_open
-    n += 256;                                               // counter
+    n += 2 * align_up(4 * (size_t)K, 256);                      // best_open, best_sorted
     if (p.nsplit > 1) {
         const size_t np = (size_t)p.nsplit * p.nclosed * (K + 1);
         n += align_up(4 * np, 256) + align_up(8 * np, 256);
@@ -1022,17 +1019,20 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
         q += align_up(bytes, 256);
         return r;
     };
-    d.open = (int32_t *)take(4 * (size_t)K);
-    d.closed = (int32_t *)take(4 * nclosed);
+    d.open[0] = (int32_t *)take(4 * (size_t)K);
+    d.open[1] = (int32_t *)take(4 * (size_t)K);
+    d.closed[0] = (int32_t *)take(4 * nclosed);
+    d.closed[1] = (int32_t *)take(4 * nclosed);
     d.tabu_until = (int32_t *)take(4 * (size_t)B);
     d.b1 = (int32_t *)take(4 * Mp);
     d.b2 = (int32_t *)take(4 * Mp);
     d.o1 = (int32_t *)take(4 * Mp);
-    d.acc = (Acc *)take(sizeof(Acc) * kStripes * (K + 1));
+    d.acc[0] = (Acc *)take(sizeof(Acc) * kStripes * (K + 1));
+    d.acc[1] = (Acc *)take(sizeof(Acc) * kStripes * (K + 1));
     d.cand = (Candidate *)take(sizeof(Candidate) * std::max(p.ngroups, 1));
     d.st = (SolveState *)take(sizeof(SolveState));
     d.best_open = (int32_t *)take(4 * (size_t)K);
-    d.counter = (unsigned int *)take(256);
+    d.best_sorted = (int32_t *)take(4 * (size_t)K);
     d.part_cov = nullptr;
     d.part_dist = nullptr;
     if (p.nsplit > 1) {
@@ -1079,49 +1079,6 @@ fs_status engine_reset(const EngineTables &t, int32_t maxB, int32_t Kmax, hipStr
     return FS_OK;
 }
 
-fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, hipStream_t s)
-{
-    if (t.nrefresh == 0) return FS_OK;
-    TimedLaunch timed(1, s);
-    const size_t lds = 16 * (size_t)(c.Kmax + 1) + 4 * (size_t)c.Kmax;
-    k_refresh<<<t.nrefresh, kBlock, lds, s>>>(t.desc, t.refresh, 0);
-    FS_HIP(hipGetLastError());
-    return FS_OK;
-}
-
-fs_status engine_init_score(const EngineTables &t, const EngineConfig &c, hipStream_t s)
-{
-    const size_t lds = 16 * (size_t)(c.Kmax + 1) + 4 * (size_t)c.Kmax;
-    if (t.nrefresh > 0) {
-        k_refresh<<<t.nrefresh, kBlock, lds, s>>>(t.desc, t.refresh, 1);
-        FS_HIP(hipGetLastError());
-    }
-    k_init_score<<<t.ninst, kBlock, 0, s>>>(t.desc);
-    FS_HIP(hipGetLastError());
-    return FS_OK;
-}
-
-fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, hipStream_t s)
-{
-    TimedLaunch timed(0, s);
-    switch (c.J) {
-    case 1: return launch_sweep_j<1>(t, c, s);
-    case 2: return launch_sweep_j<2>(t, c, s);
-    case 4: return launch_sweep_j<4>(t, c, s);
-    case 8: return launch_sweep_ju<8, 1>(t, c, s);
-    default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
-    }
-}
-
-fs_status engine_finalize(const EngineTables &t, const EngineConfig &c, hipStream_t s)
-{
-    if (c.fused) return FS_OK;
-    TimedLaunch timed(2, s);
-    k_finalize<<<t.ninst, kBlock, 0, s>>>(t.desc);
-    FS_HIP(hipGetLastError());
-    return FS_OK;
-}
-
 fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nrow_tiles,
                             int32_t Bmax, hipStream_t s)
 {
@@ -1134,19 +1091,48 @@ fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nr
     return FS_OK;
 }
 
-fs_status engine_outputs(const EngineTables &t, int32_t Kmax, fs_score *scores, int32_t *errors,
-                         hipStream_t s)
+fs_status engine_init(const EngineTables &t, const EngineConfig &c, hipStream_t s)
 {
-    k_outputs<<<t.ninst, kBlock, 4 * (size_t)Kmax + 16, s>>>(t.desc, scores, errors);
+    if (t.nrefresh > 0) {
+        k_refresh<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh, 0);
+        FS_HIP(hipGetLastError());
+    }
+    k_init_score<<<t.ninst, kBlock, 0, s>>>(t.desc);
     FS_HIP(hipGetLastError());
     return FS_OK;
 }
 
-fs_status engine_assign(const int32_t *C, int64_t ldc, int32_t M, const int32_t *open_sorted,
-                        int32_t K, int32_t R, int32_t *out, hipStream_t s)
+fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
-    k_assign<<<(M + kBlock - 1) / kBlock, kBlock, 0, s>>>(C, ldc, M, open_sorted, K, R, out);
+    TimedLaunch timed(0, s);
+    switch (c.J) {
+    case 1: return launch_sweep_j<1>(t, c, step, s);
+    case 2: return launch_sweep_j<2>(t, c, step, s);
+    case 4: return launch_sweep_j<4>(t, c, step, s);
+    case 8: return launch_sweep_ju<8, 1>(t, c, step, s);
+    default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
+    }
+}
+
+fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+{
+    if (t.nrefresh == 0) return FS_OK;
+    TimedLaunch timed(1, s);
+    k_refresh<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh, step);
     FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+fs_status engine_outputs(const EngineTables &t, const EngineConfig &c, fs_score *scores,
+                         int32_t *errors, hipStream_t s)
+{
+    (void)c;
+    k_outputs<<<t.ninst, kBlock, 0, s>>>(t.desc, scores, errors);
+    FS_HIP(hipGetLastError());
+    if (t.nrefresh > 0) {
+        k_assign<<<t.nrefresh, kBlock, 0, s>>>(t.desc, t.refresh);
+        FS_HIP(hipGetLastError());
+    }
     return FS_OK;
 }
 

@@ -73,11 +73,10 @@ struct Candidate {
 };
 static_assert(sizeof(Candidate) == 32, "candidate layout");
 
-// Per-solve search state, resident in device memory so that every iteration
-// launches the same kernels with the same arguments.
+// Per-solve search state, resident in device memory.
 struct SolveState {
-    int32_t t;          // iterations completed
     int32_t stopped;    // local search reached a local optimum
+    int32_t pad0;
     int32_t cur_cov;
     int32_t best_cov;
     int64_t cur_dist;

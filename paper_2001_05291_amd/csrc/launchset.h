@@ -41,11 +41,11 @@ struct LaunchSet {
 
 // Validates nothing (callers do); plans, allocates (stream-ordered) and
 // uploads.  target_wg: sweep workgroups wanted per instance (mission splits).
-fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int target_wg,
-                           LaunchSet &ls, hipStream_t s);
+fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, LaunchSet &ls,
+                           hipStream_t s);
 
-// Reset, ranking, initial value, then N iterations (each: sweep with fused
-// finish or standalone finish, then refresh except after the last).
+// Reset, ranking, initial state, then N iterations (each: sweep, then
+// refresh, which applies the chosen move and recomputes the state).
 fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s);
 
 // Outputs kernel, then scores and error iterations to the host (synchronises).

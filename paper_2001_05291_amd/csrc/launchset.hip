@@ -16,8 +16,8 @@ namespace {
 size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 }  // namespace
 
-fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int target_wg,
-                           LaunchSet &ls, hipStream_t s)
+fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, LaunchSet &ls,
+                           hipStream_t s)
 {
     const int n = (int)specs.size();
     if (n < 1) return fail(FS_E_INVALID, "empty launch set");
@@ -38,8 +38,11 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int t
     cfg.J = choose_rows_per_group(sorted_ncl[n / 2], Kmax);
     cfg.U = choose_unroll(cfg.J);
     cfg.vec4 = vec4;
-    cfg.nt = env_int("FS_SWEEP_NT", 1) != 0;
-    cfg.fused = fused && env_int("FS_FUSED_FINALIZE", 1) != 0;
+    // non-temporal row loads once the tables outgrow what the 256 MB
+    // Infinity Cache keeps across iterations
+    size_t table_bytes = 0;
+    for (const InstSpec &p : specs) table_bytes += (size_t)p.B * p.M * 4;
+    cfg.nt = env_int("FS_SWEEP_NT", table_bytes > ((size_t)96 << 20)) != 0;
     cfg.Kmax = Kmax;
     ls.Bmax = Bmax;
 
@@ -75,7 +78,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int t
     size_t total = o_ws;
     for (int i = 0; i < n; ++i) {
         ws_off[i] = total;
-        total += instance_bytes(specs[i].B, specs[i].M, specs[i].K, plans[i], specs[i].N);
+        total += instance_bytes(specs[i].B, specs[i].M, specs[i].K, plans[i]);
         if (!specs[i].init_host) total += a256(8 * (size_t)specs[i].B);
     }
     FS_HIP(hipMallocAsync(&ls.dev, total, s));
@@ -97,6 +100,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int t
         d.N = p.N;
         d.mode = p.mode;
         d.active = 1;
+        d.start_step = 0;
         d.trace = p.trace;
         d.sc_cov = p.sc_cov;
         d.sc_dist = p.sc_dist;
@@ -105,11 +109,12 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int t
         if (p.init_host) {
             d.need_rank = 0;
             d.sums = nullptr;
-            // open list as given; closed list = the complement, ascending id
-            d.open = lists_dev + lpos;
+            // lists of S_1 (parity 1): open list as given, closed list = the
+            // complement in ascending id order
+            d.open[1] = lists_dev + lpos;
             memcpy(lists_host + lpos, p.init_host, 4 * (size_t)p.K);
             lpos += p.K;
-            d.closed = lists_dev + lpos;
+            d.closed[1] = lists_dev + lpos;
             std::vector<unsigned char> in(p.B, 0);
             for (int32_t k = 0; k < p.K; ++k) in[p.init_host[k]] = 1;
             size_t c = 0;
@@ -118,8 +123,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, bool fused, int t
             lpos += std::max(p.B - p.K, 1);
         } else {
             d.need_rank = 1;
-            d.sums = (int64_t *)(base + ws_off[i] +
-                                 instance_bytes(p.B, p.M, p.K, plans[i], p.N));
+            d.sums = (int64_t *)(base + ws_off[i] + instance_bytes(p.B, p.M, p.K, plans[i]));
         }
     }
     memcpy(head.data() + o_desc, ls.descs.data(), sizeof(InstDesc) * n);
@@ -152,11 +156,10 @@ fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s)
 {
     FS_TRY(engine_reset(ls.tabs, ls.Bmax, ls.cfg.Kmax, s));
     if (ls.any_rank) FS_TRY(engine_rank_lists(ls.tabs, ls.rank_rows, ls.nrank_rows, ls.Bmax, s));
-    FS_TRY(engine_init_score(ls.tabs, ls.cfg, s));
+    FS_TRY(engine_init(ls.tabs, ls.cfg, s));
     for (int32_t t = 1; t <= N; ++t) {
-        FS_TRY(engine_sweep(ls.tabs, ls.cfg, s));
-        FS_TRY(engine_finalize(ls.tabs, ls.cfg, s));
-        if (t < N) FS_TRY(engine_refresh(ls.tabs, ls.cfg, s));
+        FS_TRY(engine_sweep(ls.tabs, ls.cfg, t, s));
+        FS_TRY(engine_refresh(ls.tabs, ls.cfg, t, s));
     }
     return FS_OK;
 }
@@ -165,7 +168,7 @@ fs_status collect_results(LaunchSet &ls, std::vector<fs_score> &scores,
                           std::vector<int32_t> &errors, hipStream_t s)
 {
     const int n = ls.tabs.ninst;
-    FS_TRY(engine_outputs(ls.tabs, ls.cfg.Kmax, ls.d_scores, ls.d_errors, s));
+    FS_TRY(engine_outputs(ls.tabs, ls.cfg, ls.d_scores, ls.d_errors, s));
     scores.assign(n, fs_score{});
     errors.assign(n, 0);
     FS_HIP(hipMemcpyAsync(scores.data(), ls.d_scores, sizeof(fs_score) * n, hipMemcpyDeviceToHost, s));

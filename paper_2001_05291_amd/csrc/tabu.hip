@@ -47,10 +47,10 @@ extern "C" fs_status fs_move_scores(const int32_t *C, int64_t ldc, int32_t B, in
     sp.sc_cov = cov_out;
     sp.sc_dist = dist_out;
     LaunchSet ls;
-    FS_TRY(build_launch_set({sp}, /*fused=*/false, env_int("FS_SWEEP_TARGET_WG", 2048), ls, s));
+    FS_TRY(build_launch_set({sp}, env_int("FS_SWEEP_TARGET_WG", 256), ls, s));
     FS_TRY(engine_reset(ls.tabs, ls.Bmax, ls.cfg.Kmax, s));
-    FS_TRY(engine_init_score(ls.tabs, ls.cfg, s));
-    FS_TRY(engine_sweep(ls.tabs, ls.cfg, s));
+    FS_TRY(engine_init(ls.tabs, ls.cfg, s));
+    FS_TRY(engine_sweep(ls.tabs, ls.cfg, 1, s));
     FS_HIP(hipStreamSynchronize(s));
     return FS_OK;
 }
@@ -99,7 +99,7 @@ extern "C" fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int
     sp.best_out = best_open_out;
     sp.assign_out = assign_out;
     LaunchSet ls;
-    FS_TRY(build_launch_set({sp}, /*fused=*/true, env_int("FS_SWEEP_TARGET_WG", 2048), ls, s));
+    FS_TRY(build_launch_set({sp}, env_int("FS_SWEEP_TARGET_WG", 256), ls, s));
     FS_TRY(run_launch_set(ls, p->iterations, s));
     std::vector<fs_score> scores;
     std::vector<int32_t> errors;

@@ -234,14 +234,14 @@ def test_tabu_random_instances():
         assert_same_result(g, o, C, R)
 
 
-@pytest.mark.parametrize("fused", [0, 1])
-def test_local_search_stop_and_geometry(fused):
-    """Local search stops early; the remaining records are no-move records
-    whichever kernel writes them (fused finish, split scoring, standalone)."""
+@pytest.mark.parametrize("J", [1, 2])
+def test_local_search_stop_and_geometry(J):
+    """Local search stops early; the remaining records are no-move records,
+    with and without the split-mission scoring kernel."""
     c = synth.CONFIGS[1]
     _, C = instance_and_table(1)
     for split in (1, 2):
-        with env(FS_FUSED_FINALIZE=fused, FS_SWEEP_SPLIT=split):
+        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
             g, o = run_both(C, c["K"], c["R"], c["T"], 40, mode=1)
         assert_same_result(g, o, C, c["R"])
         assert g.trace["moved"][-1] == 0
@@ -272,9 +272,9 @@ def test_plans_are_bit_identical():
     _, C = instance_and_table(2)
     Cd = padded_table(C, c["M"])
     ref = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
-    for J, split, U, fused in ((1, 1, 1, 1), (2, 4, 2, 0), (4, 9, 4, 1), (8, 2, 1, 0),
-                               (4, 1, 2, 1), (1, 3, 4, 1)):
-        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_FUSED_FINALIZE=fused):
+    for J, split, U, nt in ((1, 1, 1, 1), (2, 4, 2, 0), (4, 9, 4, 1), (8, 2, 1, 0),
+                            (4, 1, 2, 1), (1, 3, 4, 1)):
+        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt):
             g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
         assert np.array_equal(g.trace, ref.trace)
         assert np.array_equal(g.best_open.cpu().numpy(), ref.best_open.cpu().numpy())
