@@ -40,13 +40,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3),
-                    help="workload size preset (default: 500 bases x 20,000 missions)")
+    ap.add_argument("--workload", default="medium", choices=("small", "medium", "large"),
+                    help="size preset (default medium: 500 bases x 20,000 missions)")
     ap.add_argument("--cpu-iters", type=int, default=None,
                     help="Tabu iterations of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_traffic.json"),
-                    help="HBM traffic per sweep launch measured with rocprofv3 counters")
+    ap.add_argument("--iterations", type=int, default=None,
+                    help="override the Tabu iteration count (short profiled runs only)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -59,10 +61,14 @@ def main():
     from paper_2001_05291_amd import fleetstage as fs
     from paper_2001_05291_amd import synth
 
-    c = synth.CONFIGS[args.config]
+    from paper_2001_05291_amd import profiling
+
+    c = synth.WORKLOADS[args.workload]
     B, M, K, R, T, N = c["B"], c["M"], c["K"], c["R"], c["T"], c["N"]
+    if args.iterations is not None:
+        N = args.iterations
     log(f"[bench] building instance B={B} H={c['H']} M={M} K={K} R={R} T={T} N={N}")
-    inst = synth.config_instance(args.config)
+    inst = synth.workload_instance(args.workload)
     dev = torch.device("cuda:0")
     bases = torch.from_numpy(inst.bases).to(dev)
     missions = torch.from_numpy(inst.missions).to(dev)
@@ -90,7 +96,6 @@ def main():
     elapsed = time.perf_counter() - t0
     sweep_ms, sweep_n = fs.timing_read("sweep")
     refresh_ms, refresh_n = fs.timing_read("refresh")
-    fin_ms, fin_n = fs.timing_read("finalize")
     fs.timing_enable(False)
     log(f"[bench] timed {args.steps} steps in {elapsed:.4f} s")
 
@@ -103,14 +108,8 @@ def main():
     sweep_bytes = (B - K) * M * 4 + 12 * M
     sweep_avg_s = (sweep_ms / max(sweep_n, 1)) / 1e3
     achieved = sweep_bytes / sweep_avg_s / 1e9 if sweep_n else None
-    traffic = None
-    try:
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        if tj.get("workload") == f"config{args.config}":
-            traffic = tj.get("bytes_per_launch")
-    except (OSError, ValueError):
-        pass
+    traffic = profiling.read_traffic(
+        os.path.join(ROOT, "profiles", f"k_sweep_{args.workload}_traffic.md"), args.workload)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "kernel": "k_sweep", "bytes_per_launch": sweep_bytes,
@@ -119,7 +118,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        n_cpu = args.cpu_iters or {1: 100, 2: 150, 3: 3}[args.config]
+        n_cpu = args.cpu_iters or {"small": 100, "medium": 150, "large": 3}[args.workload]
         log(f"[bench] cpu baseline: oracle table + {n_cpu} Tabu iterations")
         Co, _ = oracle.cost_table(inst.bases, inst.missions, want_cf=False)
         t1 = time.perf_counter()
@@ -145,7 +144,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"config{args.config}: tabu swap search, B={B} bases, "
+        "config": {"workload": f"{args.workload}: tabu swap search, B={B} bases, "
                                f"M={M} missions, K={K} vehicles, R={R} m, T={T}, N={N}",
                    "B": B, "H": c["H"], "M": M, "K": K, "R": R, "T": T, "N": N,
                    "seed": c["seed"], "parallelism": "single GPU"},
@@ -153,10 +152,15 @@ def main():
         "cpu_baseline": cpu,
         "detail": {"sweep_ms_per_launch": sweep_ms / max(sweep_n, 1),
                    "refresh_ms_per_launch": refresh_ms / max(refresh_n, 1),
-                   "finalize_ms_per_launch": fin_ms / max(fin_n, 1),
                    "best_coverage": r.coverage, "best_distance_m": r.distance,
                    "best_iter": r.best_iter},
     }
+    if args.copy_probe:
+        x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 536870912 B read, 536870912 B written")
     print(json.dumps(line), flush=True)
 
 

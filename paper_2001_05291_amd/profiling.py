@@ -1,0 +1,140 @@
+"""Summaries of rocprofv3 output databases (rocpd SQLite) for ``profiles/``.
+
+    python -m paper_2001_05291_amd.profiling trace DB OUT.md --title T --command CMD
+    python -m paper_2001_05291_amd.profiling traffic --fetch DB --write DB --kernel RE
+        --copy RE --copy-bytes N --algorithmic-bytes N OUT.md --command CMD...
+
+``trace`` writes per-kernel launch statistics (calls, mean / min / max
+duration).  ``traffic`` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per
+dispatch, summed over the counter instances of a dispatch) of one kernel into
+bytes per launch, each scaled by what the same counter reads for a plain copy
+kernel of known size, and records the hash of the kernel source it was taken
+with so that a stale figure is not reported for changed code.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import re
+import sqlite3
+import statistics
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+SWEEP_SOURCE = os.path.join(PKG, "csrc", "engine.hip")
+
+
+def source_hash(path: str = SWEEP_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "").replace("fs::", "")
+    n = re.sub(r"\(.*\)$", "", n)
+    return n.replace("void ", "")
+
+
+def kernel_stats(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
+        "from kernels group by name order by sum(duration) desc").fetchall()
+    con.close()
+    return [(short_name(n), c, a / 1e3, lo / 1e3, hi / 1e3, s / 1e6) for n, c, a, lo, hi, s in rows]
+
+
+def counter_per_dispatch(db: str, kernel_re: str, counter: str):
+    """Mean over dispatches of kernels matching kernel_re of the counter's value
+    summed over its instances; also the number of dispatches."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select name, dispatch_id, sum(counter_value) from pmc_events where counter_name = ? "
+        "group by dispatch_id, name", (counter,)).fetchall()
+    con.close()
+    vals = [v for n, _, v in rows if re.search(kernel_re, short_name(n or ""))]
+    if not vals:
+        raise SystemExit(f"no {counter} samples for kernels matching {kernel_re!r} in {db}")
+    return statistics.fmean(vals), len(vals)
+
+
+def write_trace(db: str, out: str, title: str, command: str):
+    lines = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | mean (us) | min (us) | max (us) | total (ms) |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for n, c, a, lo, hi, s in kernel_stats(db):
+        lines.append(f"| `{n}` | {c} | {a:.2f} | {lo:.2f} | {hi:.2f} | {s:.3f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def write_traffic(fetch_db: str, write_db: str, kernel_re: str, copy_re: str, copy_bytes: int,
+                  algorithmic: int, out: str, commands, workload: str):
+    f_k, n_f = counter_per_dispatch(fetch_db, kernel_re, "FETCH_SIZE")
+    w_k, n_w = counter_per_dispatch(write_db, kernel_re, "WRITE_SIZE")
+    f_c, _ = counter_per_dispatch(fetch_db, copy_re, "FETCH_SIZE")
+    w_c, _ = counter_per_dispatch(write_db, copy_re, "WRITE_SIZE")
+    f_scale = copy_bytes / (f_c * 1024.0)
+    w_scale = copy_bytes / (w_c * 1024.0)
+    fetch_b = f_k * 1024.0 * f_scale
+    write_b = w_k * 1024.0 * w_scale
+    total = fetch_b + write_b
+    lines = [f"# HBM traffic of `{kernel_re}` ({workload})", "",
+             "Commands:", "", "```", *commands, "```", "",
+             f"- FETCH_SIZE per dispatch: {f_k:.1f} KiB over {n_f} dispatches; copy kernel "
+             f"(`{copy_re}`, {copy_bytes} B read): {f_c:.1f} KiB -> scale {f_scale:.4f}",
+             f"- WRITE_SIZE per dispatch: {w_k:.1f} KiB over {n_w} dispatches; copy kernel "
+             f"({copy_bytes} B written): {w_c:.1f} KiB -> scale {w_scale:.4f}",
+             f"- scaled fetch {fetch_b:.0f} B + write {write_b:.0f} B per launch",
+             f"- algorithmic bytes per launch: {algorithmic} "
+             f"(traffic / algorithmic = {total / algorithmic:.3f})", "",
+             f"workload: {workload}",
+             f"traffic_bytes_per_launch: {total:.0f}",
+             f"source_sha256: {source_hash()}"]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return total
+
+
+def read_traffic(path: str, workload: str):
+    """Traffic per launch recorded in a summary, or None when it is missing,
+    for another workload, or taken with a different kernel source."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(\w+): (.+)$", text, re.M))
+    if kv.get("workload") != workload or kv.get("source_sha256") != source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("out")
+    t.add_argument("--title", required=True)
+    t.add_argument("--command", required=True)
+    r = sub.add_parser("traffic")
+    r.add_argument("out")
+    r.add_argument("--fetch", required=True)
+    r.add_argument("--write", required=True)
+    r.add_argument("--kernel", required=True)
+    r.add_argument("--copy", required=True)
+    r.add_argument("--copy-bytes", type=int, required=True)
+    r.add_argument("--algorithmic-bytes", type=int, required=True)
+    r.add_argument("--workload", required=True)
+    r.add_argument("--command", action="append", default=[])
+    a = ap.parse_args()
+    if a.cmd == "trace":
+        write_trace(a.db, a.out, a.title, a.command)
+    else:
+        write_traffic(a.fetch, a.write, a.kernel, a.copy, a.copy_bytes, a.algorithmic_bytes,
+                      a.out, a.command, a.workload)
+
+
+if __name__ == "__main__":
+    main()

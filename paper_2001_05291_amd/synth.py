@@ -181,19 +181,19 @@ def make_instance(seed: int, B: int, H: int, M: int, K: int = 0, R: int = 0,
                     meta=dict(meta))
 
 
-# Workload presets: sizes of the five configurations this package is measured on.
-CONFIGS = {
-    1: dict(seed=0, B=40, H=120, M=200, K=5, R=1_200_000, T=7, N=100),
-    2: dict(seed=0, B=500, H=1_500, M=20_000, K=30, R=1_000_000, T=15, N=500),
-    3: dict(seed=0, B=4_000, H=10_000, M=100_000, K=64, R=900_000, T=25, N=200),
+# Single-instance workload presets (seed, sizes, range in metres, tenure, iterations).
+WORKLOADS = {
+    "small": dict(seed=0, B=40, H=120, M=200, K=5, R=1_200_000, T=7, N=100),
+    "medium": dict(seed=0, B=500, H=1_500, M=20_000, K=30, R=1_000_000, T=15, N=500),
+    "large": dict(seed=0, B=4_000, H=10_000, M=100_000, K=64, R=900_000, T=25, N=200),
 }
-BATCH_CONFIG = dict(n=1024, size_seed=4, T=10, N=200)
+BATCH = dict(n=1024, size_seed=4, T=10, N=200)
 SERVE_LARGE = dict(B=2_000, H=6_000, M=50_000, K=48)
 
 
-def config_instance(cfg: int) -> Instance:
-    c = dict(CONFIGS[cfg])
-    return make_instance(**c, config=cfg)
+def workload_instance(name: str) -> Instance:
+    c = dict(WORKLOADS[name])
+    return make_instance(**c, workload=name)
 
 
 def batch_sizes(n: int = 1024, size_seed: int = 4):

@@ -46,5 +46,5 @@ def assert_trace_equal(gpu_trace, ref, n=None):
 
 
 def instance_and_table(cfg):
-    inst = synth.config_instance(cfg)
+    inst = synth.workload_instance(cfg)
     return inst, oracle_table(inst)

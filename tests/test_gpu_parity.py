@@ -69,7 +69,7 @@ def check_cost_table(inst, legs=3, ldc=None):
 
 
 def test_cost_table_config1():
-    assert check_cost_table(synth.config_instance(1)) == 0
+    assert check_cost_table(synth.workload_instance("small")) == 0
 
 
 def test_cost_table_ragged_and_two_legs():
@@ -81,8 +81,8 @@ def test_cost_table_ragged_and_two_legs():
 def test_cost_table_full_size_sampled():
     """Largest single-GPU table (4,000 bases x 100,000 missions) built on the
     GPU; sampled base rows x mission columns checked against the oracle."""
-    c = synth.CONFIGS[3]
-    inst = synth.config_instance(3)
+    c = synth.WORKLOADS["large"]
+    inst = synth.workload_instance("large")
     Cg, Cfg = fs.build_cost_table(to_dev(inst.bases), to_dev(inst.missions), want_cf=True)
     rng = np.random.default_rng(0)
     bi = np.sort(rng.choice(c["B"], 48, replace=False))
@@ -102,7 +102,7 @@ def test_cost_table_full_size_sampled():
 @pytest.mark.parametrize("ldc_pad", [0, 4, 1])
 def test_rank_matches_oracle(ldc_pad):
     rng = np.random.default_rng(2 + ldc_pad)
-    cases = [oracle_table(synth.config_instance(1)), oracle_table(synth.config_instance(2))]
+    cases = [oracle_table(synth.workload_instance("small")), oracle_table(synth.workload_instance("medium"))]
     cases += [rng.integers(0, 3, size=(300, 257)).astype(np.int32)]   # many equal sums
     for C in cases:
         B, M = C.shape
@@ -129,8 +129,8 @@ def check_scores(C, S, R, ldc=None):
 
 
 def test_move_scores_config1_and_2():
-    for cfg in (1, 2):
-        c = synth.CONFIGS[cfg]
+    for cfg in ("small", "medium"):
+        c = synth.WORKLOADS[cfg]
         _, C = instance_and_table(cfg)
         S = oracle.rank_bases(C, c["K"])[0]
         check_scores(C, S.tolist(), c["R"])
@@ -183,17 +183,17 @@ def assert_same_result(g, o, C, R):
         assert np.array_equal(g.assign.cpu().numpy(), oracle.assign(C, o.best_open, R))
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", ["small", "medium"])
 def test_tabu_full_trace_configs(cfg):
-    c = synth.CONFIGS[cfg]
+    c = synth.WORKLOADS[cfg]
     _, C = instance_and_table(cfg)
     g, o = run_both(C, c["K"], c["R"], c["T"], c["N"], ldc=(c["M"] + 3) // 4 * 4)
     assert_same_result(g, o, C, c["R"])
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", ["small", "medium"])
 def test_local_search_configs(cfg):
-    c = synth.CONFIGS[cfg]
+    c = synth.WORKLOADS[cfg]
     _, C = instance_and_table(cfg)
     g, o = run_both(C, c["K"], c["R"], c["T"], c["N"], mode=1)
     assert_same_result(g, o, C, c["R"])
@@ -238,8 +238,8 @@ def test_tabu_random_instances():
 def test_local_search_stop_and_geometry(J):
     """Local search stops early; the remaining records are no-move records,
     with and without the split-mission scoring kernel."""
-    c = synth.CONFIGS[1]
-    _, C = instance_and_table(1)
+    c = synth.WORKLOADS["small"]
+    _, C = instance_and_table("small")
     for split in (1, 2):
         with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
             g, o = run_both(C, c["K"], c["R"], c["T"], 40, mode=1)
@@ -268,8 +268,8 @@ def test_special_cases():
 
 def test_plans_are_bit_identical():
     """The result does not depend on the sweep's launch geometry."""
-    c = synth.CONFIGS[2]
-    _, C = instance_and_table(2)
+    c = synth.WORKLOADS["medium"]
+    _, C = instance_and_table("medium")
     Cd = padded_table(C, c["M"])
     ref = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
     for J, split, U, nt in ((1, 1, 1, 1), (2, 4, 2, 0), (4, 9, 4, 1), (8, 2, 1, 0),
@@ -284,8 +284,8 @@ def test_full_size_prefix_and_invariants():
     """Largest single-GPU instance (4,000 bases, 100,000 missions, 64
     vehicles): the first iterations equal the oracle's; every record of the
     200-iteration trace is consistent with a recount of its placement."""
-    c = synth.CONFIGS[3]
-    inst = synth.config_instance(3)
+    c = synth.WORKLOADS["large"]
+    inst = synth.workload_instance("large")
     C = oracle_table(inst)
     Cd = to_dev(C)
     g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], c["N"])

@@ -318,8 +318,8 @@ def test_tabu_thread_count_invariant():
 def test_config1_tabu_against_exhaustive_optimum():
     """Configuration 1 (40 bases, 200 missions, 5 vehicles, R = 1,200 km): the
     Tabu result never beats the optimum over all C(40,5) = 658,008 placements."""
-    c = synth.CONFIGS[1]
-    inst = synth.config_instance(1)
+    c = synth.WORKLOADS["small"]
+    inst = synth.workload_instance("small")
     C, _ = oracle.cost_table(inst.bases, inst.missions, want_cf=False)
     r = oracle.tabu(C, c["K"], c["R"], c["T"], c["N"])
     best, cov, dist, n = oracle.brute_optimum(C, c["K"], c["R"])
