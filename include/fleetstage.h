@@ -192,6 +192,84 @@ typedef struct {
 fs_status fs_tabu_solve_batch(const fs_instance *inst, int32_t n, const fs_params *p,
                               fs_score *scores_out, void *stream);
 
+/* Repositioning server (continuous batching).  Section 1 motivates quick
+ * repositioning of vehicles when demand changes, and the conclusion quick
+ * updates of the model; the server keeps cost tables resident on the device,
+ * takes requests that redraw some missions of a registered instance and
+ * re-solve it (Tabu search, Section 4.3) warm-started from that instance's
+ * previous best placement, and runs all admitted requests together: one
+ * batched iteration at a time, admitting new requests between iterations as
+ * slots and device memory free up.  A request's result depends only on its
+ * instance's missions after its redraw, its warm start and its parameters, so
+ * it is identical alone and in the mix.
+ *
+ * Requests on one instance run in submission order (each starts from the
+ * previous one's result); requests on different instances run concurrently.
+ * Cost tables count against hbm_budget_bytes together with the workspaces of
+ * running requests; tables of idle instances are evicted least recently used
+ * first and rebuilt from the kept coordinates when needed again. */
+typedef struct {
+    int64_t hbm_budget_bytes;  /* > 0 */
+    int32_t max_slots;         /* requests solved concurrently, 1..4096 */
+    int32_t device;            /* HIP device ordinal */
+    double earth_radius_m;     /* 0 selects 6,371,000 m */
+    int32_t legs;              /* 3 or 2, as for fs_build_cost_table */
+    int32_t pad;
+} fs_serve_config;
+
+typedef struct {
+    int64_t resident_bytes;    /* cost tables currently on the device */
+    int64_t workspace_bytes;   /* workspaces of running requests */
+    int64_t evictions;         /* tables evicted so far */
+    int64_t rebuilds;          /* tables built (first use or after eviction) */
+    int64_t steps;             /* batched iterations run */
+    int64_t completed;         /* requests finished */
+    int32_t running;           /* requests in slots now */
+    int32_t queued;            /* requests waiting for a slot */
+} fs_serve_stats;
+
+typedef struct fs_server fs_server;
+
+/* Starts a server on cfg->device with its own stream and scheduler thread.
+ * Errors: FS_E_INVALID for a bad config; FS_E_DEVICE if the device cannot be
+ * used. */
+fs_status fs_serve_open(const fs_serve_config *cfg, fs_server **out);
+
+/* Registers an instance: base coordinates (host, B x 2 degrees) and mission
+ * coordinates (host, M x 4 degrees) are copied; K vehicles; range R.  The
+ * cost table is built on first use.  Returns the instance id.
+ * Errors: FS_E_INVALID (sizes, K > 1024, R), FS_E_BUDGET if the instance's
+ * table plus one workspace can never fit the budget, FS_E_CLOSED. */
+fs_status fs_serve_register(fs_server *sv, const double *base_latlon_deg, int32_t B,
+                            const double *mission_pd_deg, int32_t M, int32_t K,
+                            int32_t range_m, int64_t *instance_id);
+
+/* Submits a repositioning request: missions mission_ids[0..n) (host) of the
+ * instance get the new coordinates new_pd_deg (host, n x 4 degrees), then the
+ * instance is re-solved with p->tenure, p->iterations and p->mode (p->range_m
+ * is ignored), warm-started from its previous best placement (base ranking
+ * for its first request).  n may be 0.  Thread-safe.
+ * Errors: FS_E_NOTFOUND (instance), FS_E_INVALID (ids, params), FS_E_CLOSED,
+ * FS_E_DEVICE after a device failure. */
+fs_status fs_serve_submit(fs_server *sv, int64_t instance_id, const int32_t *mission_ids,
+                          const double *new_pd_deg, int32_t n, const fs_params *p,
+                          uint64_t *ticket);
+
+/* FS_PENDING while the request runs or waits; FS_OK with the best placement
+ * (host, K ids ascending), its score and the latency from submission to
+ * completion in seconds; the ticket is then released.  Thread-safe.
+ * Errors: FS_E_NOTFOUND (unknown or already collected ticket), or the
+ * request's own failure status. */
+fs_status fs_serve_poll(fs_server *sv, uint64_t ticket, int32_t *open_out, fs_score *score_out,
+                        double *latency_s);
+
+/* Counters of the server.  Thread-safe. */
+fs_status fs_serve_stats_get(fs_server *sv, fs_serve_stats *out);
+
+/* Stops the scheduler, drops the requests still waiting or running, frees
+ * every device buffer and the handle (which must not be used afterwards). */
+fs_status fs_serve_close(fs_server *sv);
+
 /* Diagnostics: device time of the search kernels, for roofline reporting.
  * While enabled (on != 0), every launch of a kernel group is bracketed by a
  * pair of HIP events recorded on the stream it is launched on; groups are

@@ -11,6 +11,8 @@
 //
 // This file is compiled with -ffp-contract=off so that every product and sum
 // is rounded separately, in the order written.
+#include <algorithm>
+
 #include "fs_internal.h"
 
 namespace fs {
@@ -84,7 +86,54 @@ __global__ __launch_bounds__(kBlock) void k_cost_table(const double *__restrict_
     }
 }
 
+// Recomputes the columns of the given missions: ids[i] receives the costs of
+// the mission with coordinates mpd[i].  grid: x = id blocks, y = base groups.
+// Ids outside [0, M) are skipped.
+__global__ __launch_bounds__(kBlock) void k_cost_columns(const double *__restrict__ bases, int32_t B,
+                                                         const int32_t *__restrict__ ids,
+                                                         const double *__restrict__ mpd, int32_t n,
+                                                         int32_t M, double two_r, int32_t legs,
+                                                         int32_t *__restrict__ C, int64_t ldc)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = ids[i];
+    if (m < 0 || m >= M) return;
+    const double *q = mpd + 4 * (int64_t)i;
+    const double phi_p = q[0] * kDeg2Rad, psi_p = q[1] * kDeg2Rad;
+    const double phi_d = q[2] * kDeg2Rad, psi_d = q[3] * kDeg2Rad;
+    const double cos_p = cos(phi_p), cos_d = cos(phi_d);
+    const double pd = haversine(phi_p, psi_p, cos_p, phi_d, psi_d, cos_d, two_r);
+    for (int32_t b0 = blockIdx.y * kBasesPerBlock; b0 < B; b0 += gridDim.y * kBasesPerBlock)
+#pragma unroll
+    for (int q2 = 0; q2 < kBasesPerBlock; ++q2) {
+        const int32_t b = b0 + q2;
+        if (b >= B) break;
+        const double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
+        const double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
+        const double cos_b = cos(phi_b);
+        const double bp = haversine(phi_b, psi_b, cos_b, phi_p, psi_p, cos_p, two_r);
+        const double db = haversine(phi_d, psi_d, cos_d, phi_b, psi_b, cos_b, two_r);
+        const double v = (legs == 3) ? (bp + pd) + db : bp + db;
+        C[(int64_t)b * ldc + m] = (int32_t)rint(v);
+    }
+}
+
 }  // namespace
+
+fs_status launch_cost_columns(const double *bases, int32_t B, const int32_t *ids,
+                              const double *mpd, int32_t n, int32_t M, double radius,
+                              int32_t legs, int32_t *C, int64_t ldc, hipStream_t s)
+{
+    if (n <= 0) return FS_OK;
+    const double r = radius == 0.0 ? 6371000.0 : radius;
+    const int32_t gy = std::min<int32_t>((B + kBasesPerBlock - 1) / kBasesPerBlock, 65535);
+    dim3 g((n + kBlock - 1) / kBlock, gy);
+    k_cost_columns<<<g, kBlock, 0, s>>>(bases, B, ids, mpd, n, M, 2.0 * r, legs, C, ldc);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
 }  // namespace fs
 
 extern "C" fs_status fs_build_cost_table(const double *base_latlon_deg, int32_t B,

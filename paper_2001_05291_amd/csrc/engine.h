@@ -101,8 +101,9 @@ fs_status engine_reset(const EngineTables &t, int32_t maxB, int32_t Kmax, hipStr
 // ids) and closed list (the complement, ascending).
 fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nrow_tiles,
                             int32_t Bmax, hipStream_t s);
-// State of the initial placement, then cur = best = its value.
-fs_status engine_init(const EngineTables &t, const EngineConfig &c, hipStream_t s);
+// State of the initial placement, then cur = best = its value.  step0 is the
+// launch step at which the instances' iteration 0 ends (their start_step).
+fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s);
 // Scores every swap of every instance and keeps each row group's best
 // admissible move.
 fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step,

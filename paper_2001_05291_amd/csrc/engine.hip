@@ -1091,10 +1091,10 @@ fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nr
     return FS_OK;
 }
 
-fs_status engine_init(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s)
 {
     if (t.nrefresh > 0) {
-        k_refresh<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh, 0);
+        k_refresh<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh, step0);
         FS_HIP(hipGetLastError());
     }
     k_init_score<<<t.ninst, kBlock, 0, s>>>(t.desc);

@@ -113,4 +113,11 @@ fs_status launch_sort_ids(const int32_t *ids, int32_t K, int32_t *out, hipStream
 fs_status launch_rank(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K,
                       int32_t *order_out, int64_t *sums, hipStream_t s);
 
+// Cost-table columns of changed missions (cost_table.hip): column ids[i]
+// gets the round-trip costs of the mission with coordinates mpd[i] (device
+// arrays); ids outside [0, M) are skipped.
+fs_status launch_cost_columns(const double *bases, int32_t B, const int32_t *ids,
+                              const double *mpd, int32_t n, int32_t M, double radius,
+                              int32_t legs, int32_t *C, int64_t ldc, hipStream_t s);
+
 }  // namespace fs

@@ -156,7 +156,7 @@ fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s)
 {
     FS_TRY(engine_reset(ls.tabs, ls.Bmax, ls.cfg.Kmax, s));
     if (ls.any_rank) FS_TRY(engine_rank_lists(ls.tabs, ls.rank_rows, ls.nrank_rows, ls.Bmax, s));
-    FS_TRY(engine_init(ls.tabs, ls.cfg, s));
+    FS_TRY(engine_init(ls.tabs, ls.cfg, 0, s));
     for (int32_t t = 1; t <= N; ++t) {
         FS_TRY(engine_sweep(ls.tabs, ls.cfg, t, s));
         FS_TRY(engine_refresh(ls.tabs, ls.cfg, t, s));

@@ -52,6 +52,19 @@ class Instance(ctypes.Structure):
 
 assert ctypes.sizeof(Instance) == 64
 
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("earth_radius_m", ctypes.c_double),
+                ("legs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("resident_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("evictions", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("running", ctypes.c_int32), ("queued", ctypes.c_int32)]
+
 _lib = None
 
 
@@ -81,6 +94,20 @@ def lib():
     L.fs_tabu_solve_batch.restype = i32
     L.fs_tabu_solve_batch.argtypes = [ctypes.POINTER(Instance), i32, ctypes.POINTER(Params),
                                       ctypes.POINTER(Score), vp]
+    L.fs_serve_open.restype = i32
+    L.fs_serve_open.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
+    L.fs_serve_register.restype = i32
+    L.fs_serve_register.argtypes = [vp, vp, i32, vp, i32, i32, i32, ctypes.POINTER(i64)]
+    L.fs_serve_submit.restype = i32
+    L.fs_serve_submit.argtypes = [vp, i64, vp, vp, i32, ctypes.POINTER(Params),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+    L.fs_serve_poll.restype = i32
+    L.fs_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(Score),
+                                ctypes.POINTER(f64)]
+    L.fs_serve_stats_get.restype = i32
+    L.fs_serve_stats_get.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    L.fs_serve_close.restype = i32
+    L.fs_serve_close.argtypes = [vp]
     L.fs_timing_enable.restype = i32
     L.fs_timing_enable.argtypes = [i32]
     L.fs_timing_read.restype = i32
@@ -254,3 +281,86 @@ def timing_read(group: str):
     n = ctypes.c_int64()
     _check(lib().fs_timing_read(group.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+@dataclass
+class ServeResult:
+    best_open: np.ndarray     # host int32 K, ascending
+    coverage: int
+    distance: int
+    best_iter: int
+    latency_s: float
+
+
+class Server:
+    """Repositioning server (continuous batching over resident cost tables).
+    Coordinates and mission redraws are host arrays (copied by the server)."""
+
+    def __init__(self, hbm_budget_bytes: int = 200 << 30, max_slots: int = 64, device: int = 0,
+                 earth_radius_m: float = 0.0, legs: int = 3):
+        cfg = ServeConfig(int(hbm_budget_bytes), int(max_slots), int(device),
+                          float(earth_radius_m), int(legs), 0)
+        h = ctypes.c_void_p()
+        _check(lib().fs_serve_open(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._K = {}
+
+    def register(self, bases, missions, K: int, range_m: int) -> int:
+        b = np.ascontiguousarray(bases, dtype=np.float64)
+        m = np.ascontiguousarray(missions, dtype=np.float64)
+        iid = ctypes.c_int64()
+        _check(lib().fs_serve_register(self._h, b.ctypes.data, b.shape[0], m.ctypes.data,
+                                       m.shape[0], int(K), int(range_m), ctypes.byref(iid)))
+        self._K[iid.value] = int(K)
+        return int(iid.value)
+
+    def submit(self, instance_id: int, mission_ids, new_pd, tenure: int, iterations: int,
+               mode: int = 0) -> int:
+        ids = np.ascontiguousarray(mission_ids, dtype=np.int32)
+        pd = np.ascontiguousarray(new_pd, dtype=np.float64).reshape(-1, 4)
+        p = Params(int(tenure), int(iterations), 0, int(mode))
+        t = ctypes.c_uint64()
+        _check(lib().fs_serve_submit(self._h, int(instance_id), ids.ctypes.data if ids.size else None,
+                                     pd.ctypes.data if ids.size else None, int(ids.size),
+                                     ctypes.byref(p), ctypes.byref(t)))
+        return int(t.value), int(instance_id)
+
+    def poll(self, ticket):
+        """ServeResult when done, None while pending (ticket is (id, instance))."""
+        tk, iid = ticket
+        out = np.zeros(self._K[iid], dtype=np.int32)
+        sc = Score()
+        lat = ctypes.c_double()
+        st = lib().fs_serve_poll(self._h, tk, out.ctypes.data, ctypes.byref(sc), ctypes.byref(lat))
+        if st == FS_PENDING:
+            return None
+        _check(st)
+        return ServeResult(out, int(sc.coverage), int(sc.distance), int(sc.best_iter),
+                           float(lat.value))
+
+    def wait(self, ticket, timeout: float = 120.0, interval: float = 2e-4):
+        import time
+        t_end = time.monotonic() + timeout
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"request {ticket} not done after {timeout} s")
+            time.sleep(interval)
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(lib().fs_serve_stats_get(self._h, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in ServeStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(lib().fs_serve_close(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

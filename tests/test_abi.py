@@ -54,3 +54,16 @@ def test_version_and_validation_without_gpu(library):
     assert rc == -1
     library.fs_last_error.restype = ctypes.c_char_p
     assert b"NULL" in library.fs_last_error()
+
+
+def test_server_config_validated_before_device_use(library):
+    class Cfg(ctypes.Structure):
+        _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                    ("device", ctypes.c_int32), ("earth_radius_m", ctypes.c_double),
+                    ("legs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+    library.fs_serve_open.restype = ctypes.c_int32
+    library.fs_serve_open.argtypes = [ctypes.POINTER(Cfg), ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    for cfg in (Cfg(1 << 30, 0, 0, 0.0, 3, 0), Cfg(0, 4, 0, 0.0, 3, 0),
+                Cfg(1 << 30, 4, 0, 0.0, 5, 0), Cfg(1 << 30, 4, -1, 0.0, 3, 0)):
+        assert library.fs_serve_open(ctypes.byref(cfg), ctypes.byref(h)) == -1

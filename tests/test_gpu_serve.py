@@ -1,0 +1,150 @@
+"""GPU tests of the repositioning server: every request's result equals the
+plain path (one tabu_solve per request, replayed in order with the same
+redraws and warm starts), whatever the number of slots and with evictions;
+and one request against the CPU oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2001_05291_amd import synth
+
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fs():
+    from paper_2001_05291_amd import fleetstage
+    fleetstage.lib()
+    return fleetstage
+
+
+def make_workload(n_inst, n_req, seed, sizes=((20, 120), (100, 1500), (2, 12))):
+    rng = np.random.default_rng(seed)
+    insts = []
+    for i in range(n_inst):
+        B = int(rng.integers(*sizes[0]))
+        M = int(rng.integers(*sizes[1]))
+        K = int(rng.integers(sizes[2][0], min(sizes[2][1], B - 1) + 1))
+        R = int(rng.integers(800_000, 1_400_000))
+        inst = synth.make_instance(seed=100 + i, B=B, H=3 * B, M=M)
+        insts.append(dict(inst=inst, K=K, R=R))
+    reqs = []
+    for q in range(n_req):
+        i = int(rng.integers(0, n_inst))
+        inst = insts[i]["inst"]
+        ids, pairs = synth.perturbation(seed + i, inst.hospitals.shape[0], inst.M, 0.1, request=q)
+        pd = synth.missions_from_pairs(inst.hospitals, pairs)
+        reqs.append(dict(inst=i, ids=ids, pd=pd))
+    return insts, reqs
+
+
+def plain_replay(fs, insts, reqs, T, N, mode=0):
+    """One fs.tabu_solve per request, in submission order per instance."""
+    coords = [w["inst"].missions.copy() for w in insts]
+    prev = [None] * len(insts)
+    out = []
+    for r in reqs:
+        i = r["inst"]
+        coords[i][r["ids"]] = r["pd"]
+        w = insts[i]
+        C, _ = fs.build_cost_table(to_dev(w["inst"].bases), to_dev(coords[i]))
+        res = fs.tabu_solve(C, w["K"], w["R"], T, N, mode=mode, init_open=prev[i],
+                            M=w["inst"].M, want_trace=False, want_assign=False)
+        prev[i] = res.best_open.clone()
+        out.append((res.best_open.cpu().numpy(), res.coverage, res.distance, res.best_iter))
+    return out
+
+
+def serve_all(fs, insts, reqs, T, N, mode=0, **cfg):
+    with fs.Server(**cfg) as sv:
+        ids = [sv.register(w["inst"].bases, w["inst"].missions, w["K"], w["R"]) for w in insts]
+        tickets = [sv.submit(ids[r["inst"]], r["ids"], r["pd"], T, N, mode) for r in reqs]
+        res = [sv.wait(t) for t in tickets]
+        stats = sv.stats()
+    return res, stats
+
+
+def assert_same(served, plain):
+    for k, (s, p) in enumerate(zip(served, plain)):
+        assert np.array_equal(s.best_open, p[0]), k
+        assert (s.coverage, s.distance, s.best_iter) == p[1:], k
+
+
+@pytest.mark.parametrize("slots", [1, 4, 64])
+def test_served_equals_plain(fs, slots):
+    insts, reqs = make_workload(6, 24, seed=1)
+    plain = plain_replay(fs, insts, reqs, T=5, N=30)
+    served, stats = serve_all(fs, insts, reqs, T=5, N=30, max_slots=slots)
+    assert_same(served, plain)
+    assert stats["completed"] == 24 and stats["running"] == 0 and stats["queued"] == 0
+    assert all(s.latency_s > 0 for s in served)
+
+
+def test_local_search_requests(fs):
+    insts, reqs = make_workload(3, 9, seed=2)
+    plain = plain_replay(fs, insts, reqs, T=5, N=25, mode=1)
+    served, _ = serve_all(fs, insts, reqs, T=5, N=25, mode=1, max_slots=3)
+    assert_same(served, plain)
+
+
+def test_eviction_keeps_results(fs):
+    insts, reqs = make_workload(5, 20, seed=3, sizes=((60, 120), (1000, 2000), (3, 10)))
+    plain = plain_replay(fs, insts, reqs, T=4, N=20)
+    # room for about two tables and their workspaces at a time
+    biggest = max(w["inst"].B * ((w["inst"].M + 3) // 4 * 4) * 4 for w in insts)
+    served, stats = serve_all(fs, insts, reqs, T=4, N=20, max_slots=4,
+                              hbm_budget_bytes=int(2.2 * biggest) + (512 << 10))
+    assert_same(served, plain)
+    assert stats["evictions"] > 0 and stats["rebuilds"] > len(insts)
+
+
+def test_zero_iteration_request_and_no_redraw(fs):
+    insts, reqs = make_workload(2, 4, seed=4)
+    reqs[1]["ids"] = np.zeros(0, dtype=np.int32)
+    reqs[1]["pd"] = np.zeros((0, 4))
+    plain = plain_replay(fs, insts, reqs, T=3, N=0)
+    served, _ = serve_all(fs, insts, reqs, T=3, N=0, max_slots=2)
+    assert_same(served, plain)
+
+
+def test_first_request_against_oracle(fs):
+    insts, reqs = make_workload(1, 1, seed=5)
+    w, r = insts[0], reqs[0]
+    coords = w["inst"].missions.copy()
+    coords[r["ids"]] = r["pd"]
+    Co, _ = oracle.cost_table(w["inst"].bases, coords, want_cf=False)
+    Cg, _ = fs.build_cost_table(to_dev(w["inst"].bases), to_dev(coords))
+    if not np.array_equal(Cg[:, : w["inst"].M].cpu().numpy(), Co):
+        pytest.skip("GPU and CPU tables differ at a rounding boundary for this draw")
+    o = oracle.tabu(Co, w["K"], w["R"], 5, 30)
+    served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=2)
+    assert np.array_equal(served[0].best_open, o.best_open)
+    assert (served[0].coverage, served[0].distance, served[0].best_iter) == (
+        o.coverage, o.distance, o.best_iter)
+
+
+def test_server_errors(fs):
+    inst = synth.make_instance(seed=9, B=20, H=60, M=100)
+    with fs.Server(hbm_budget_bytes=1 << 30, max_slots=2) as sv:
+        with pytest.raises(fs.FleetstageError) as e:
+            sv.register(inst.bases, inst.missions, 21, 1_000_000)
+        assert e.value.status == fs.FS_E_INVALID
+        iid = sv.register(inst.bases, inst.missions, 4, 1_000_000)
+        with pytest.raises(fs.FleetstageError) as e:
+            sv.submit(iid + 7, [], np.zeros((0, 4)), 3, 5)
+        assert e.value.status == fs.FS_E_NOTFOUND
+        with pytest.raises(fs.FleetstageError) as e:
+            sv.submit(iid, [100], np.zeros((1, 4)), 3, 5)
+        assert e.value.status == fs.FS_E_INVALID
+        with pytest.raises(fs.FleetstageError) as e:
+            sv.poll((12345, iid))
+        assert e.value.status == fs.FS_E_NOTFOUND
+    big = synth.make_instance(seed=10, B=200, H=400, M=4000)
+    with fs.Server(hbm_budget_bytes=1 << 20, max_slots=2) as sv:
+        with pytest.raises(fs.FleetstageError) as e:
+            sv.register(big.bases, big.missions, 5, 1_000_000)
+        assert e.value.status == fs.FS_E_BUDGET
