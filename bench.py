@@ -11,7 +11,16 @@ scores K*(B-K) swap moves over M missions.  It is reported for the whole step
 (cost table and ranking included in the time).  Alongside:
   roofline      the swap sweep's algorithmic bytes per launch over its average
                 launch time (HIP events on its own stream), against 8 TB/s HBM;
-  cpu_baseline  the CPU oracle on a bounded sample of the same search.
+  cpu_baseline  the CPU oracle on a bounded sample of the same search;
+  batch         the ragged batch (1,024 instances of uneven size, 200
+                iterations each): solves/s of one launch set against one solve
+                per instance, results identical;
+  serve         the repositioning load (95% small / 5% large instances, 10% of
+                the missions redrawn, 100 warm-started iterations per request):
+                solves/s at saturation and p50/p99 latency under Poisson
+                arrivals at 0.5/0.8/1.0x the plain path's saturation rate, for
+                the plain path (one table build + one solve per request) and
+                the server, whose results must be identical.
 
 Prints one JSON line.
 """
@@ -49,6 +58,15 @@ def main():
                     help="override the Tabu iteration count (short profiled runs only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the repositioning-load leg (served vs plain)")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests per stream of the repositioning-load leg")
+    ap.add_argument("--serve-pool", default="1024,64",
+                    help="resident instances of the repositioning load: small,large")
+    ap.add_argument("--serve-slots", type=int, default=128)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the ragged-batch leg (one launch set vs one solve per instance)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -87,7 +105,10 @@ def main():
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    fs.timing_enable(True)
+    # every 8th sweep / refresh launch carries dispatch-stamped events (a
+    # dispatch with events is followed by a gap, so timing all of them would
+    # slow the timed loop itself)
+    fs.timing_enable(True, every=8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -118,7 +139,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        n_cpu = args.cpu_iters or {"small": 100, "medium": 150, "large": 3}[args.workload]
+        n_cpu = args.cpu_iters or {"small": 100, "medium": 500, "large": 20}[args.workload]
         log(f"[bench] cpu baseline: oracle table + {n_cpu} Tabu iterations")
         Co, _ = oracle.cost_table(inst.bases, inst.missions, want_cf=False)
         t1 = time.perf_counter()
@@ -129,6 +150,19 @@ def main():
                "sample": f"first {n_cpu} of {N} Tabu iterations of the same instance "
                          f"(oracle cost table, not timed); {cpu_s:.2f} s"}
         log(f"[bench] cpu baseline {cpu['value']:.3e} MM-evals/s on {cpu['cores']} threads")
+
+    batch = None
+    if not args.no_batch:
+        from paper_2001_05291_amd import batchbench
+        batch = batchbench.run(fs, torch, log=log)
+
+    serve = None
+    if not args.no_serve:
+        from paper_2001_05291_amd import servebench
+        n_small, n_large = (int(x) for x in args.serve_pool.split(","))
+        serve = servebench.run(fs, torch, n_small=n_small, n_large=n_large,
+                               n_requests=args.serve_requests, slots=args.serve_slots,
+                               log=log)
 
     r = result["r"]
     line = {
@@ -150,6 +184,8 @@ def main():
                    "seed": c["seed"], "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch": batch,
+        "serve": serve,
         "detail": {"sweep_ms_per_launch": sweep_ms / max(sweep_n, 1),
                    "refresh_ms_per_launch": refresh_ms / max(refresh_n, 1),
                    "best_coverage": r.coverage, "best_distance_m": r.distance,

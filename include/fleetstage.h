@@ -271,12 +271,16 @@ fs_status fs_serve_stats_get(fs_server *sv, fs_serve_stats *out);
 fs_status fs_serve_close(fs_server *sv);
 
 /* Diagnostics: device time of the search kernels, for roofline reporting.
- * While enabled (on != 0), every launch of a kernel group is bracketed by a
- * pair of HIP events recorded on the stream it is launched on; groups are
+ * While enabled (on = n > 0), every n-th launch of each kernel group carries a
+ * pair of HIP events that the dispatch itself stamps at its start and end, on
+ * the stream it is launched on (a dispatch with events is followed by a gap of
+ * several microseconds, so sampling keeps the timed loop close to its untimed
+ * pace); on = 0 disables, a negative value is FS_E_INVALID; groups are
  * "sweep" (move evaluation, including the chunk-merge kernel when the mission
- * axis is split), "refresh" (per-mission open-base state) and "finalize"
- * (argmax and move application).  Enabling or disabling discards what was
- * recorded.  Process-wide; not meant for concurrent solves. */
+ * axis is split) and "refresh" (argmax, move application and the open-base
+ * state of the new placement); "finalize" is accepted and stays empty.
+ * Enabling or disabling discards what was recorded.  Process-wide; not meant
+ * for concurrent solves. */
 fs_status fs_timing_enable(int32_t on);
 /* Waits for the recorded events of `group`, returns their summed elapsed time
  * (milliseconds) and number of launches, and clears them.  FS_E_INVALID for an

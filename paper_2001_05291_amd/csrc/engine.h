@@ -64,6 +64,8 @@ struct EngineConfig {
     int U = 1;          // 16-byte loads per row in flight per thread
     bool vec4 = true;   // 16-byte row loads (all tables 16-byte aligned, ldc % 4 == 0)
     bool nt = true;     // non-temporal row loads
+    bool queue = true;  // score only compacted c < b2 elements (wave-level LDS queue)
+    bool wide = false;  // 1024-thread sweep workgroups (J <= 2 only)
     int Kmax = 1;
 };
 

@@ -32,6 +32,8 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
+
 #include "engine.h"
 
 namespace fs {
@@ -95,7 +97,8 @@ __device__ __forceinline__ Candidate shfl_xor_cand(const Candidate &c, int off)
 
 // Best candidate of the workgroup under the move order (a total order, so the
 // result does not depend on the reduction order); valid in every thread.
-__device__ Candidate block_best(Candidate c, Candidate *s_red /* kBlock/64 + 1 */)
+template <int BS = kBlock>
+__device__ Candidate block_best(Candidate c, Candidate *s_red /* BS/64 + 1 */)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -108,12 +111,12 @@ __device__ Candidate block_best(Candidate c, Candidate *s_red /* kBlock/64 + 1 *
     __syncthreads();
     if (threadIdx.x == 0) {
         Candidate b = s_red[0];
-        for (int w = 1; w < kBlock / 64; ++w)
+        for (int w = 1; w < BS / 64; ++w)
             if (cand_better(s_red[w], b)) b = s_red[w];
-        s_red[kBlock / 64] = b;
+        s_red[BS / 64] = b;
     }
     __syncthreads();
-    return s_red[kBlock / 64];
+    return s_red[BS / 64];
 }
 
 // G (k = 0) or L_{k-1}: sum of the accumulator stripes.
@@ -530,7 +533,7 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
     const int32_t K = d.K;
     const Acc *acc = d.acc[t & 1];
     const int32_t *op = d.open[t & 1];
-    for (int32_t k = threadIdx.x; k <= K; k += kBlock) {
+    for (int32_t k = threadIdx.x; k <= K; k += blockDim.x) {
         int32_t c;
         int64_t dd;
         acc_sum(acc, K, k, c, dd);
@@ -547,6 +550,7 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
 // Scores of the J x K moves of row group g from the per-row common sums
 // (t1c, t1d) and the per-(row, out-slot) bins; writes the optional full score
 // table and the group's best admissible candidate.
+template <int BS>
 __device__ void score_group(const InstDesc &d, int J, int32_t t, int32_t g,
                             const int32_t *s_jrow, const int32_t *s_jtabu, const SweepLds &L,
                             const int32_t *t1c, const int64_t *t1d, Candidate *s_red)
@@ -558,7 +562,7 @@ __device__ void score_group(const InstDesc &d, int J, int32_t t, int32_t g,
     const int32_t Gc = L.Lc[0];
     const int64_t Gd = L.Ld[0];
     Candidate mine{};
-    for (int32_t idx = threadIdx.x; idx < J * K; idx += kBlock) {
+    for (int32_t idx = threadIdx.x; idx < J * K; idx += BS) {
         const int32_t r = idx / K, k = idx - r * K;
         const int32_t js = g * J + r;
         if (js >= d.nclosed) continue;
@@ -586,11 +590,11 @@ __device__ void score_group(const InstDesc &d, int J, int32_t t, int32_t g,
             if (cand_better(c, mine)) mine = c;
         }
     }
-    mine = block_best(mine, s_red);
+    mine = block_best<BS>(mine, s_red);
     if (threadIdx.x == 0) d.cand[g] = mine;
 }
 
-template <int J, int U, bool NT>
+template <int BS, int J, int U, bool NT>
 __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jrow, int32_t m0,
                                            int32_t m1, int32_t *t1c, int64_t *t1d, int32_t *bc,
                                            u64 *bd)
@@ -603,11 +607,11 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
 #pragma unroll
     for (int r = 0; r < J; ++r) rows[r] = reinterpret_cast<const v4i *>(d.C + (int64_t)jrow[r] * d.ldc);
     const int32_t qend = m1 >> 2;
-    for (int32_t q0 = (m0 >> 2) + threadIdx.x; q0 < qend; q0 += U * kBlock) {
+    for (int32_t q0 = (m0 >> 2) + threadIdx.x; q0 < qend; q0 += U * BS) {
         v4i cv[U][J], vb1[U], vb2[U], vo1[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t q = q0 + u * kBlock;
+            const int32_t q = q0 + u * BS;
             if (q < qend) {
 #pragma unroll
                 for (int r = 0; r < J; ++r)
@@ -639,7 +643,123 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
     }
 }
 
-template <int J>
+// Elements with c < b2 are a few percent of the table (about 2 / (K + 1) for
+// scattered bases), but with one wave per 64 missions nearly every wave has a
+// lane that takes the scoring branch, so scoring in place costs every element
+// the branch's full instruction count.  This variant only compares in the
+// streaming loop: each wave appends the lanes that hit (c, b1, b2, o1) to a
+// queue in LDS, one queue per row, and scores 64 queued elements at a time
+// with every lane busy.  The loop runs in whole waves (lanes past the end of
+// the chunk load sentinels that never hit), so queue lengths are wave-uniform
+// and live in scalar registers; a wave only reads entries it wrote itself, so
+// no workgroup barrier is involved.
+constexpr int kQueue = 128;   // entries per (wave, row): below 64 + 64 before a drain
+
+struct QueueRow {
+    int32_t c[kQueue], b1[kQueue], b2[kQueue], o1[kQueue];
+};
+
+__device__ __forceinline__ void visit_queued(const QueueRow &qr, int32_t at, int32_t R,
+                                             int32_t &t1c, int64_t &t1d, int32_t *__restrict__ bc,
+                                             u64 *__restrict__ bd)
+{
+    const int32_t c = qr.c[at], b1 = qr.b1[at], b2 = qr.b2[at], o1 = qr.o1[at];
+    const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
+    const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+    visit(c, b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
+}
+
+template <int BS, int J, int U, bool NT>
+__device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32_t *jrow,
+                                                  int32_t m0, int32_t m1, int32_t *t1c,
+                                                  int64_t *t1d, int32_t *bc, u64 *bd)
+{
+    __shared__ QueueRow s_q[BS / 64][J];
+    const int32_t K = d.K, R = d.R;
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    gv4i *b1v = (gv4i *)d.b1;
+    gv4i *b2v = (gv4i *)d.b2;
+    gv4i *o1v = (gv4i *)d.o1;
+    gv4i *rows[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) rows[r] = (gv4i *)(d.C + (int64_t)jrow[r] * d.ldc);
+    int32_t len[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) len[r] = 0;
+    const int32_t qend = m1 >> 2;
+    for (int32_t qw = (m0 >> 2) + wave * 64; qw < qend; qw += U * BS) {
+        // lanes past the end re-read the last quad and never hit (b2 = INT32_MIN)
+        v4i cv[U][J], vb1[U], vb2[U], vo1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t q = min(qw + u * BS + lane, qend - 1);
+#pragma unroll
+            for (int r = 0; r < J; ++r)
+                cv[u][r] = NT ? __builtin_nontemporal_load(rows[r] + q) : rows[r][q];
+            vb1[u] = b1v[q];
+            vb2[u] = b2v[q];
+            vo1[u] = o1v[q];
+        }
+        // keep every load of the iteration ahead of the first use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (qw + u * BS + lane >= qend) vb2[u] = (v4i)(INT32_MIN);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int r = 0; r < J; ++r) {
+                    const bool hit = cv[u][r][e] < vb2[u][e];
+                    const u64 mask = __builtin_amdgcn_ballot_w64(hit);
+                    if (mask == 0) continue;
+                    QueueRow &qr = s_q[wave][r];
+                    if (hit) {
+                        const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(mask >> 32),
+                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)len[r]));
+                        qr.c[at] = cv[u][r][e];
+                        qr.b1[at] = vb1[u][e];
+                        qr.b2[at] = vb2[u][e];
+                        qr.o1[at] = vo1[u][e];
+                    }
+                    len[r] = __builtin_amdgcn_readfirstlane(len[r] +
+                                                            (int32_t)__builtin_popcountll(mask));
+                    if (len[r] >= 64) {
+                        // score the oldest 64, then move the rest (at most 63) down
+                        __builtin_amdgcn_wave_barrier();
+                        visit_queued(qr, lane, R, t1c[r], t1d[r], bc + r * K, bd + r * K);
+                        len[r] -= 64;
+                        int32_t c = 0, b1 = 0, b2 = 0, o1 = 0;
+                        if (lane < len[r]) {
+                            c = qr.c[64 + lane];
+                            b1 = qr.b1[64 + lane];
+                            b2 = qr.b2[64 + lane];
+                            o1 = qr.o1[64 + lane];
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane < len[r]) {
+                            qr.c[lane] = c;
+                            qr.b1[lane] = b1;
+                            qr.b2[lane] = b2;
+                            qr.o1[lane] = o1;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < J; ++r)
+        if (lane < len[r]) visit_queued(s_q[wave][r], lane, R, t1c[r], t1d[r], bc + r * K, bd + r * K);
+}
+
+template <int BS, int J>
 __device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *jrow, int32_t m0,
                                              int32_t m1, int32_t *t1c, int64_t *t1d, int32_t *bc,
                                              u64 *bd)
@@ -647,7 +767,7 @@ __device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *j
     const int32_t K = d.K, R = d.R;
     const int32_t mend = min(m1, d.M);
     const int64_t ldc = d.ldc;
-    for (int32_t m = m0 + threadIdx.x; m < mend; m += kBlock) {
+    for (int32_t m = m0 + threadIdx.x; m < mend; m += BS) {
         int32_t cv[J];
 #pragma unroll
         for (int r = 0; r < J; ++r) cv[r] = d.C[(int64_t)jrow[r] * ldc + m];
@@ -661,7 +781,7 @@ __device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *j
 }
 
 // Workgroup reduction of the per-row common sums.
-template <int J>
+template <int BS, int J>
 __device__ __forceinline__ void reduce_rows(const int32_t *t1c, const int64_t *t1d,
                                             int32_t (*s_t1c)[J], int64_t (*s_t1d)[J],
                                             int32_t *s_sum_c, int64_t *s_sum_d)
@@ -680,7 +800,7 @@ __device__ __forceinline__ void reduce_rows(const int32_t *t1c, const int64_t *t
     if (threadIdx.x < J) {
         int32_t c = 0;
         int64_t dd = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < BS / 64; ++w) {
             c += s_t1c[w][threadIdx.x];
             dd += s_t1d[w][threadIdx.x];
         }
@@ -696,7 +816,7 @@ __device__ __forceinline__ void reduce_rows(const int32_t *t1c, const int64_t *t
 __device__ void sweep_housekeeping(const InstDesc &d, int32_t t)
 {
     Acc *nxt = d.acc[(t + 1) & 1];
-    for (int32_t q = threadIdx.x; q < kStripes * (d.K + 1); q += kBlock) {
+    for (int32_t q = threadIdx.x; q < kStripes * (d.K + 1); q += blockDim.x) {
         nxt[q].cov = 0;
         nxt[q].dist = 0;
     }
@@ -716,8 +836,8 @@ __device__ void sweep_housekeeping(const InstDesc &d, int32_t t)
 // are ordered chunk-minor so that consecutive block ids (which the dispatcher
 // spreads over the XCDs) split an instance's mission axis and each XCD's L2
 // holds the b1/b2/o1 of fewer chunks.
-template <int J, int U, bool VEC4, bool NT>
-__global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ descs,
+template <int BS, int J, int U, bool VEC4, bool NT, bool Q>
+__global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs,
                                                   const Tile *__restrict__ tiles, int32_t step)
 {
     const Tile tl = tiles[blockIdx.x];
@@ -730,14 +850,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ d
     const int32_t K = d.K;
     const SweepLds L = carve_lds(smem, J, K);
     __shared__ int32_t s_jrow[J], s_jtabu[J];
-    __shared__ int32_t s_t1c[kBlock / 64][J];
-    __shared__ int64_t s_t1d[kBlock / 64][J];
+    __shared__ int32_t s_t1c[BS / 64][J];
+    __shared__ int64_t s_t1d[BS / 64][J];
     __shared__ int32_t s_sum_c[J];
     __shared__ int64_t s_sum_d[J];
-    __shared__ Candidate s_red[kBlock / 64 + 1];
+    __shared__ Candidate s_red[BS / 64 + 1];
 
     if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
-    for (int q = threadIdx.x; q < J * K; q += kBlock) {
+    for (int q = threadIdx.x; q < J * K; q += BS) {
         L.bd[q] = 0;
         L.bc[q] = 0;
     }
@@ -764,19 +884,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const InstDesc *__restrict__ d
     if (nclosed > 0) {
         const int32_t m0 = tl.sp * d.chunk;
         const int32_t m1 = min(d.Mp, m0 + d.chunk);
-        if (VEC4)
-            sweep_vec4<J, U, NT>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+        if (VEC4 && Q)
+            sweep_vec4_queued<BS, J, U, NT>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+        else if (VEC4)
+            sweep_vec4<BS, J, U, NT>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
         else
-            sweep_scalar<J>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+            sweep_scalar<BS, J>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
     }
-    reduce_rows<J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
+    reduce_rows<BS, J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
 
     if (scoring) {
-        score_group(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
+        score_group<BS>(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
     } else {
         // partial sums of this chunk: [T1, bin_0 .. bin_{K-1}] per row
         const int32_t K1 = K + 1;
-        for (int32_t idx = threadIdx.x; idx < J * K1; idx += kBlock) {
+        for (int32_t idx = threadIdx.x; idx < J * K1; idx += BS) {
             const int32_t r = idx / K1, k = idx - r * K1;
             const int32_t js = tl.g * J + r;
             if (js >= nclosed) continue;
@@ -838,7 +960,7 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
         }
     }
     __syncthreads();
-    score_group(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
+    score_group<kBlock>(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
 }
 
 // ---------------------------------------------------------------- outputs
@@ -905,36 +1027,59 @@ __global__ __launch_bounds__(kBlock) void k_assign(const InstDesc *__restrict__ 
 
 // ---------------------------------------------------------------- dispatch
 
-template <int J, int U, bool VEC4, bool NT>
-fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+template <int J, int U, bool VEC4, bool NT, bool Q>
+fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
+                         TimedLaunch &tm)
 {
-    const size_t lds = sweep_lds_bytes(J, c.Kmax);
+    const uint32_t lds = (uint32_t)sweep_lds_bytes(J, c.Kmax);
+    const bool score = t.nscore > 0;
     if (t.nsweep > 0) {
-        k_sweep<J, U, VEC4, NT><<<t.nsweep, kBlock, lds, s>>>(t.desc, t.sweep, step);
+        bool launched = false;
+        if constexpr (J <= 2) {
+            if (c.wide) {
+                hipExtLaunchKernelGGL(k_sweep<kWideBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
+                                      dim3(kWideBlock), lds, s, tm.start(),
+                                      score ? nullptr : tm.stop(), 0u, t.desc, t.sweep, step);
+                launched = true;
+            }
+        }
+        if (!launched)
+            hipExtLaunchKernelGGL(k_sweep<kBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
+                                  dim3(kBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
+                                  0u, t.desc, t.sweep, step);
         FS_HIP(hipGetLastError());
+        if (!score) tm.used();
     }
-    if (t.nscore > 0) {
-        k_score<J><<<t.nscore, kBlock, lds, s>>>(t.desc, t.score, step);
+    if (score) {
+        hipExtLaunchKernelGGL(k_score<J>, dim3(t.nscore), dim3(kBlock), lds, s,
+                              t.nsweep > 0 ? nullptr : tm.start(), tm.stop(), 0u, t.desc, t.score,
+                              step);
         FS_HIP(hipGetLastError());
+        tm.used();
     }
     return FS_OK;
 }
 
 template <int J, int U>
-fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
+                          TimedLaunch &tm)
 {
-    if (!c.vec4) return launch_sweep_t<J, 1, false, false>(t, c, step, s);
-    return c.nt ? launch_sweep_t<J, U, true, true>(t, c, step, s)
-                : launch_sweep_t<J, U, true, false>(t, c, step, s);
+    if (!c.vec4) return launch_sweep_t<J, 1, false, false, false>(t, c, step, s, tm);
+    if (c.queue)
+        return c.nt ? launch_sweep_t<J, U, true, true, true>(t, c, step, s, tm)
+                    : launch_sweep_t<J, U, true, false, true>(t, c, step, s, tm);
+    return c.nt ? launch_sweep_t<J, U, true, true, false>(t, c, step, s, tm)
+                : launch_sweep_t<J, U, true, false, false>(t, c, step, s, tm);
 }
 
 template <int J>
-fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
+                         TimedLaunch &tm)
 {
     switch (c.U) {
-    case 1: return launch_sweep_ju<J, 1>(t, c, step, s);
-    case 2: return launch_sweep_ju<J, 2>(t, c, step, s);
-    case 4: return launch_sweep_ju<J, 4>(t, c, step, s);
+    case 1: return launch_sweep_ju<J, 1>(t, c, step, s, tm);
+    case 2: return launch_sweep_ju<J, 2>(t, c, step, s, tm);
+    case 4: return launch_sweep_ju<J, 4>(t, c, step, s, tm);
     default: return fail(FS_E_INTERNAL, "unsupported sweep unroll %d", c.U);
     }
 }
@@ -1104,12 +1249,12 @@ fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step
 
 fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
-    TimedLaunch timed(0, s);
+    TimedLaunch timed(0);
     switch (c.J) {
-    case 1: return launch_sweep_j<1>(t, c, step, s);
-    case 2: return launch_sweep_j<2>(t, c, step, s);
-    case 4: return launch_sweep_j<4>(t, c, step, s);
-    case 8: return launch_sweep_ju<8, 1>(t, c, step, s);
+    case 1: return launch_sweep_j<1>(t, c, step, s, timed);
+    case 2: return launch_sweep_j<2>(t, c, step, s, timed);
+    case 4: return launch_sweep_j<4>(t, c, step, s, timed);
+    case 8: return launch_sweep_ju<8, 1>(t, c, step, s, timed);
     default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
     }
 }
@@ -1117,9 +1262,12 @@ fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t ste
 fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
     if (t.nrefresh == 0) return FS_OK;
-    TimedLaunch timed(1, s);
-    k_refresh<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh, step);
+    TimedLaunch timed(1);
+    hipExtLaunchKernelGGL(k_refresh, dim3(t.nrefresh), dim3(kBlock),
+                          (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), 0u,
+                          t.desc, t.refresh, step);
     FS_HIP(hipGetLastError());
+    timed.used();
     return FS_OK;
 }
 

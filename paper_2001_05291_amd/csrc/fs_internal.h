@@ -35,24 +35,39 @@ fs_status fail(fs_status code, const char *fmt, ...);
 // RAII bracket of one launch of a kernel group (0 sweep, 1 refresh,
 // 2 finalize) with HIP events when timing is enabled; a no-op otherwise.
 bool timing_on();
+// Timing of the calling thread's launches is skipped while suppressed.
+void timing_suppress(bool on);
+// While set (non-null), the calling thread's next timed launch stamps this
+// caller-owned event pair instead of recording into a group (the autotuner's
+// trial launches).
+void timing_borrow(hipEvent_t start, hipEvent_t stop);
+
 class TimedLaunch {
   public:
-    TimedLaunch(int group, hipStream_t s);
+    // Events for one launch (or a chain of launches) of a group when timing
+    // is on, else null events.  They go to hipExtLaunchKernelGGL, which has
+    // the dispatch itself stamp its start and end, so timing adds no packet
+    // between kernels.  Call used() once they have been handed to a launch.
+    explicit TimedLaunch(int group);
     ~TimedLaunch();
     TimedLaunch(const TimedLaunch &) = delete;
     TimedLaunch &operator=(const TimedLaunch &) = delete;
+    hipEvent_t start() const { return a_; }
+    hipEvent_t stop() const { return b_; }
+    void used() { used_ = a_ != nullptr; }
 
   private:
     int group_;
-    hipStream_t s_;
     hipEvent_t a_ = nullptr, b_ = nullptr;
-    bool armed_ = false;
+    bool used_ = false;
+    bool borrowed_ = false;
 };
 
 // ---------------------------------------------------------------- limits
 
 constexpr int kMaxK = 1024;          // open slots handled by the sweep's LDS bins
 constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
+constexpr int kWideBlock = 1024;     // sweep workgroups when there are few row groups
 
 // ---------------------------------------------------------------- device state
 

@@ -44,6 +44,11 @@ struct LaunchSet {
 fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, LaunchSet &ls,
                            hipStream_t s);
 
+// Picks the fastest plan-preserving sweep variant for this launch set's shape
+// (cached per shape; skipped when the sweep variant is fixed by environment).
+// Needs the initial state (engine_init) in place.
+fs_status tune_sweep(LaunchSet &ls, hipStream_t s);
+
 // Reset, ranking, initial state, then N iterations (each: sweep, then
 // refresh, which applies the chosen move and recomputes the state).
 fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s);

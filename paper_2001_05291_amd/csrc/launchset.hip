@@ -1,7 +1,12 @@
 // Launch-set construction shared by the single solve, the batch and the
 // server.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "launchset.h"
 
@@ -43,6 +48,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     size_t table_bytes = 0;
     for (const InstSpec &p : specs) table_bytes += (size_t)p.B * p.M * 4;
     cfg.nt = env_int("FS_SWEEP_NT", table_bytes > ((size_t)96 << 20)) != 0;
+    cfg.queue = env_int("FS_SWEEP_QUEUE", 1) != 0;
     cfg.Kmax = Kmax;
     ls.Bmax = Bmax;
 
@@ -54,6 +60,13 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     }
     std::vector<Tile> sweep, score, refresh, rank_rows;
     build_tiles(plans, Mp, sweep, score, refresh);
+    // few long row groups: 1024-thread workgroups keep four times as many
+    // waves in flight, so each thread has fewer dependent load rounds
+    std::vector<int32_t> chunks(n);
+    for (int i = 0; i < n; ++i) chunks[i] = plans[i].chunk;
+    std::sort(chunks.begin(), chunks.end());
+    cfg.wide = env_int("FS_SWEEP_WIDE", cfg.J <= 2 && sweep.size() < 1024 &&
+                                            chunks[n / 2] >= 8192) != 0 && cfg.J <= 2;
     size_t list_ints = 0;
     for (int i = 0; i < n; ++i) {
         if (specs[i].init_host) {
@@ -152,11 +165,131 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     return FS_OK;
 }
 
+namespace {
+
+// Shape of a launch set as far as the sweep's speed is concerned.
+struct TuneKey {
+    int64_t ninst, nsweep, nscore, rows, missions;
+    int32_t J, Kmax, vec4, nt;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(ninst, nsweep, nscore, rows, missions, J, Kmax, vec4, nt) <
+               std::tie(o.ninst, o.nsweep, o.nscore, o.rows, o.missions, o.J, o.Kmax, o.vec4,
+                        o.nt);
+    }
+};
+
+struct Tuned {
+    int U;
+    bool queue, wide;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuned> g_tuned;
+
+bool user_fixed_sweep()
+{
+    return getenv("FS_SWEEP_U") || getenv("FS_SWEEP_QUEUE") || getenv("FS_SWEEP_WIDE");
+}
+
+}  // namespace
+
+// Sweep variants that leave the plan (and therefore the workspace) as it is:
+// loads in flight per thread, queued scoring, 1024-thread workgroups.  Each is
+// timed on the sweep of iteration 1, which may run any number of times: it
+// only writes its row groups' candidates (and split partials) and clears the
+// accumulators the next refresh fills.  All variants give identical results.
+// The fastest is kept for this shape for the rest of the process.
+fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
+{
+    if (!ls.cfg.vec4 || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
+        env_int("FS_AUTOTUNE", 1) == 0)
+        return FS_OK;
+    TuneKey key{ls.tabs.ninst, ls.tabs.nsweep, ls.tabs.nscore, 0, 0,
+                ls.cfg.J, ls.cfg.Kmax, ls.cfg.vec4, ls.cfg.nt};
+    for (const InstDesc &d : ls.descs) {
+        key.rows += d.nclosed;
+        key.missions += d.Mp;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            ls.cfg.U = it->second.U;
+            ls.cfg.queue = it->second.queue;
+            ls.cfg.wide = it->second.wide;
+            return FS_OK;
+        }
+    }
+    std::vector<EngineConfig> cands;
+    for (int U : {1, 2, 4})
+        for (int q = 0; q < 2; ++q)
+            for (int w = 0; w < (ls.cfg.J <= 2 ? 2 : 1); ++w) {
+                EngineConfig c = ls.cfg;
+                c.U = U;
+                c.queue = q != 0;
+                c.wide = w != 0;
+                cands.push_back(c);
+            }
+    // each candidate: one untimed launch, then kReps launches, each stamped
+    // by its own dispatch (no marker packets between the launches)
+    constexpr int kReps = 2;
+    std::vector<hipEvent_t> ev(2 * kReps * cands.size(), nullptr);
+    fs_status st = FS_OK;
+    for (size_t i = 0; i < ev.size() && st == FS_OK; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) st = fail(FS_E_DEVICE, "autotune: event");
+    timing_suppress(true);
+    for (size_t i = 0; i < cands.size() && st == FS_OK; ++i) {
+        st = engine_sweep(ls.tabs, cands[i], 1, s);
+        for (int r = 0; r < kReps && st == FS_OK; ++r) {
+            const size_t e = 2 * (kReps * i + r);
+            timing_borrow(ev[e], ev[e + 1]);
+            st = engine_sweep(ls.tabs, cands[i], 1, s);
+            timing_borrow(nullptr, nullptr);
+        }
+    }
+    timing_suppress(false);
+    size_t best = 0;
+    float best_ms = 0.f;
+    if (st == FS_OK && hipStreamSynchronize(s) != hipSuccess)
+        st = fail(FS_E_DEVICE, "autotune: synchronize");
+    const bool verbose = env_int("FS_AUTOTUNE_LOG", 0) != 0;
+    for (size_t i = 0; i < cands.size() && st == FS_OK; ++i) {
+        float ms = 0.f;
+        for (int r = 0; r < kReps; ++r) {
+            const size_t e = 2 * (kReps * i + r);
+            float one = 0.f;
+            if (hipEventElapsedTime(&one, ev[e], ev[e + 1]) != hipSuccess) {
+                st = fail(FS_E_DEVICE, "autotune: elapsed time");
+                break;
+            }
+            ms = r == 0 ? one : std::min(ms, one);
+        }
+        if (st != FS_OK) break;
+        if (verbose)
+            fprintf(stderr, "[autotune] J=%d U=%d queue=%d wide=%d: %.1f us per sweep\n",
+                    cands[i].J, cands[i].U, (int)cands[i].queue, (int)cands[i].wide,
+                    1000.0 * ms);
+        if (i == 0 || ms < best_ms) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != FS_OK) return st;
+    ls.cfg = cands[best];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = Tuned{ls.cfg.U, ls.cfg.queue, ls.cfg.wide};
+    return FS_OK;
+}
+
 fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s)
 {
     FS_TRY(engine_reset(ls.tabs, ls.Bmax, ls.cfg.Kmax, s));
     if (ls.any_rank) FS_TRY(engine_rank_lists(ls.tabs, ls.rank_rows, ls.nrank_rows, ls.Bmax, s));
     FS_TRY(engine_init(ls.tabs, ls.cfg, 0, s));
+    if (N >= 1) FS_TRY(tune_sweep(ls, s));
     for (int32_t t = 1; t <= N; ++t) {
         FS_TRY(engine_sweep(ls.tabs, ls.cfg, t, s));
         FS_TRY(engine_refresh(ls.tabs, ls.cfg, t, s));

@@ -121,6 +121,9 @@ struct Server {
     int32_t *d_errors = nullptr;
     char *d_arena = nullptr;
     size_t arena_cap = 0, arena_off = 0;
+    std::vector<char *> retired_arenas;   // outgrown this round; freed next round
+    Tile *d_tiles = nullptr;          // sweep then refresh tiles of the running slots
+    size_t tiles_cap = 0;             // in tiles
     char *h_stage[2] = {nullptr, nullptr};
     size_t stage_cap = 0, stage_off = 0;
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
@@ -203,6 +206,9 @@ fs_status Server::begin_stage(size_t need)
             FS_HIP(hipHostMalloc((void **)&h_stage[q], stage_cap, hipHostMallocDefault));
     }
     arena_off = 0;
+    // every launch that used an outgrown arena was enqueued last round
+    for (char *a : retired_arenas) FS_HIP(hipFreeAsync(a, s));
+    retired_arenas.clear();
     return FS_OK;
 }
 
@@ -246,11 +252,11 @@ fs_status Server::arena_take(size_t n, char **out)
         const size_t cap = std::max(2 * arena_cap, a256(arena_off + n) + (1u << 20));
         char *fresh = nullptr;
         FS_HIP(hipMallocAsync((void **)&fresh, cap, s));
-        if (d_arena) FS_HIP(hipFreeAsync(d_arena, s));
+        // launches of this round may still be enqueued against the old one
+        if (d_arena) retired_arenas.push_back(d_arena);
         d_arena = fresh;
         arena_cap = cap;
         arena_off = 0;
-        tiles_dirty = true;   // tables placed earlier in the old arena are gone
     }
     *out = d_arena + arena_off;
     arena_off += n;
@@ -469,14 +475,22 @@ fs_status Server::rebuild_tables()
             refresh.push_back(Tile{(int32_t)i, g, 0, 0});
     }
     FS_TRY(upload(d_desc, descs.data(), sizeof(InstDesc) * descs.size()));
-    char *p = nullptr;
-    FS_TRY(arena_take(sizeof(Tile) * sweep.size(), &p));
-    FS_TRY(upload(p, sweep.data(), sizeof(Tile) * sweep.size()));
-    tabs.sweep = (const Tile *)p;
-    tabs.nsweep = (int)sweep.size();
-    FS_TRY(arena_take(sizeof(Tile) * refresh.size(), &p));
-    FS_TRY(upload(p, refresh.data(), sizeof(Tile) * refresh.size()));
-    tabs.refresh = (const Tile *)p;
+    // the tables stay until the set of running slots changes; a copy into
+    // them is stream-ordered after every kernel that read the old contents
+    const size_t ntiles = sweep.size() + refresh.size();
+    if (ntiles > tiles_cap) {
+        const size_t cap = std::max(ntiles, 2 * tiles_cap);
+        Tile *fresh = nullptr;
+        FS_HIP(hipMallocAsync((void **)&fresh, sizeof(Tile) * cap, s));
+        if (d_tiles) FS_HIP(hipFreeAsync(d_tiles, s));
+        d_tiles = fresh;
+        tiles_cap = cap;
+    }
+    sweep.insert(sweep.end(), refresh.begin(), refresh.end());
+    FS_TRY(upload(d_tiles, sweep.data(), sizeof(Tile) * ntiles));
+    tabs.sweep = d_tiles;
+    tabs.nsweep = (int)(ntiles - refresh.size());
+    tabs.refresh = d_tiles + tabs.nsweep;
     tabs.nrefresh = (int)refresh.size();
     tabs.score = nullptr;
     tabs.nscore = 0;
@@ -491,8 +505,6 @@ fs_status Server::round_once(bool &idle)
 {
     ++round;
     FS_TRY(begin_stage(0));
-    // tile tables live in the arena, which every round starts over
-    tiles_dirty = true;
     // retire finished slots whose results have arrived
     for (size_t i = 0; i < slots.size(); ++i) {
         Slot &sl = slots[i];
@@ -530,8 +542,8 @@ fs_status Server::round_once(bool &idle)
         I.waiting.pop_front();
         it = pending.erase(it);
     }
-    // descriptors and tiles (every round: the arena starts over)
-    FS_TRY(rebuild_tables());
+    // descriptors and tiles when the set of slots has changed
+    if (tiles_dirty) FS_TRY(rebuild_tables());
     // initial state of the requests admitted this round
     for (size_t i = 0; i < slots.size(); ++i) {
         Slot &sl = slots[i];
@@ -679,6 +691,9 @@ void Server::release_device()
         if (sl.h_best) (void)hipHostFree(sl.h_best);
     }
     if (d_arena) (void)hipFreeAsync(d_arena, s);
+    for (char *a : retired_arenas) (void)hipFreeAsync(a, s);
+    retired_arenas.clear();
+    if (d_tiles) (void)hipFreeAsync(d_tiles, s);
     if (s) (void)hipStreamSynchronize(s);
     if (d_desc) (void)hipFree(d_desc);
     if (d_scores) (void)hipFree(d_scores);

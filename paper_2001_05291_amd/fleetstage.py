@@ -139,11 +139,27 @@ def _stream(stream=None):
 
 
 def _table(C, M):
-    if C.dim() != 2 or C.dtype != torch.int32:
-        raise TypeError("cost table must be a 2-D int32 tensor (bases x pitch)")
-    B, ldc = C.shape
-    M = ldc if M is None else int(M)
+    """(B, M, ldc) of a cost table: a (B, M) tensor whose rows are contiguous
+    and ldc elements apart (what build_cost_table returns: a view of a B x ldc
+    buffer), or a B x ldc buffer with the mission count M given explicitly."""
+    if not isinstance(C, torch.Tensor) or C.dim() != 2 or C.dtype != torch.int32:
+        raise TypeError("cost table must be a 2-D int32 tensor (bases x missions)")
+    if not C.is_cuda:
+        raise TypeError("expected a device (cuda/hip) tensor")
+    B, width = C.shape
+    if C.stride(1) != 1 and width > 1:
+        raise ValueError("cost table rows must be contiguous")
+    ldc = C.stride(0)
+    if ldc < width:
+        raise ValueError("cost table row stride is smaller than its width")
+    M = width if M is None else int(M)
+    if M > width:
+        raise ValueError(f"M={M} exceeds the table width {width}")
     return B, M, ldc
+
+
+def _table_ptr(C):
+    return ctypes.c_void_p(C.data_ptr())
 
 
 def version() -> str:
@@ -152,9 +168,10 @@ def version() -> str:
 
 def build_cost_table(bases, missions, earth_radius_m: float = 0.0, legs: int = 3,
                      ldc: int | None = None, want_cf: bool = False, stream=None):
-    """C (int32, B x ldc) and optionally Cf (float64) from device coordinates:
-    bases (B, 2) and missions (M, 4) float64 degrees.  ldc defaults to M
-    rounded up to a multiple of 4 (16-byte aligned rows)."""
+    """C (int32) and optionally Cf (float64) from device coordinates: bases
+    (B, 2) and missions (M, 4) float64 degrees.  Both are (B, M) views of
+    buffers with row pitch ldc, which defaults to M rounded up to a multiple
+    of 4 (16-byte aligned rows)."""
     B, M = int(bases.shape[0]), int(missions.shape[0])
     ldc = (M + 3) // 4 * 4 if ldc is None else int(ldc)
     dev = bases.device
@@ -163,7 +180,8 @@ def build_cost_table(bases, missions, earth_radius_m: float = 0.0, legs: int = 3
     _check(lib().fs_build_cost_table(_ptr(bases, torch.float64), B,
                                      _ptr(missions, torch.float64), M, float(earth_radius_m),
                                      int(legs), _ptr(C), ldc, _ptr(Cf), _stream(stream)))
-    return C, Cf
+    # (B, M) views of the padded rows: the other calls read M and ldc from them
+    return C[:, :M], (Cf[:, :M] if Cf is not None else None)
 
 
 def rank_bases(C, K: int, M: int | None = None, stream=None):
@@ -173,7 +191,7 @@ def rank_bases(C, K: int, M: int | None = None, stream=None):
     op = torch.empty(K, dtype=torch.int32, device=dev)
     order = torch.empty(K, dtype=torch.int32, device=dev)
     sums = torch.empty(B, dtype=torch.int64, device=dev)
-    _check(lib().fs_rank_bases(_ptr(C), ldc, B, M, int(K), _ptr(op), _ptr(order), _ptr(sums),
+    _check(lib().fs_rank_bases(_table_ptr(C), ldc, B, M, int(K), _ptr(op), _ptr(order), _ptr(sums),
                                _stream(stream)))
     return op, order, sums
 
@@ -186,7 +204,7 @@ def move_scores(C, open_ids, range_m: int, M: int | None = None, stream=None):
     K = int(op.numel())
     cov = torch.empty((K, B), dtype=torch.int32, device=dev)
     dist = torch.empty((K, B), dtype=torch.int64, device=dev)
-    _check(lib().fs_move_scores(_ptr(C), ldc, B, M, _ptr(op), K, int(range_m), _ptr(cov),
+    _check(lib().fs_move_scores(_table_ptr(C), ldc, B, M, _ptr(op), K, int(range_m), _ptr(cov),
                                 _ptr(dist), _stream(stream)))
     return cov, dist
 
@@ -216,7 +234,7 @@ def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int 
     if init_open is not None:
         init = init_open.to(device=dev, dtype=torch.int32).contiguous()
     sc = Score()
-    _check(lib().fs_tabu_solve(_ptr(C), ldc, B, M, int(K), ctypes.byref(p), _ptr(init),
+    _check(lib().fs_tabu_solve(_table_ptr(C), ldc, B, M, int(K), ctypes.byref(p), _ptr(init),
                                _ptr(best), ctypes.byref(sc), _ptr(assign),
                                _ptr(trace) if n > 0 else None, _stream(stream)))
     tr = None
@@ -270,9 +288,10 @@ def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
     return res
 
 
-def timing_enable(on: bool = True) -> None:
-    """Bracket every sweep / refresh / finalize launch with HIP events."""
-    _check(lib().fs_timing_enable(1 if on else 0))
+def timing_enable(on: bool = True, every: int = 1) -> None:
+    """Time every `every`-th sweep / refresh launch with dispatch-stamped HIP
+    events (off with on=False)."""
+    _check(lib().fs_timing_enable(int(every) if on else 0))
 
 
 def timing_read(group: str):

@@ -48,6 +48,8 @@ _S_HOSP_LAT, _S_HOSP_LON = 8, 9
 _S_PICK, _S_DROP = 10, 11
 _S_SIZES = 12
 _S_PERTURB_PICK, _S_PERTURB_NEW = 13, 14
+_S_ARRIVAL, _S_REQ_KIND, _S_REQ_PICK = 15, 16, 17
+_S_POOL_RANGE = 18
 
 
 def _mix64(z: np.ndarray) -> np.ndarray:
@@ -188,7 +190,10 @@ WORKLOADS = {
     "large": dict(seed=0, B=4_000, H=10_000, M=100_000, K=64, R=900_000, T=25, N=200),
 }
 BATCH = dict(n=1024, size_seed=4, T=10, N=200)
+# Repositioning requests: 95% on instances shaped like the ragged batch, 5% on
+# large ones; each redraws 10% of the missions and runs 100 iterations.
 SERVE_LARGE = dict(B=2_000, H=6_000, M=50_000, K=48)
+SERVE = dict(seed=5, large_fraction=0.05, redraw_fraction=0.1, T=10, N=100)
 
 
 def workload_instance(name: str) -> Instance:
@@ -222,3 +227,35 @@ def perturbation(seed: int, H: int, M: int, fraction: float = 0.1, request: int 
     pairs = gen_mission_pairs(seed, H, n, first=request * M,
                               streams=(_S_PERTURB_NEW, _S_PERTURB_NEW + 100))
     return ids, pairs
+
+
+def serve_pool(n_small: int, n_large: int, size_seed: int = 4):
+    """Resident instances of the repositioning load: n_small shaped like the
+    ragged batch (data seed = index) and n_large of SERVE_LARGE's size with a
+    range drawn like the batch's (data seed = 100000 + index)."""
+    pool = [make_instance(seed=k, **s) for k, s in enumerate(batch_sizes(n_small, size_seed))]
+    rng = uniform_int(size_seed, _S_POOL_RANGE, np.arange(n_large), 800_000, 1_400_000)
+    for k in range(n_large):
+        pool.append(make_instance(seed=100_000 + k, R=int(rng[k]), **SERVE_LARGE))
+    return pool
+
+
+def request_stream(n: int, rate: float, n_small: int, n_large: int, seed: int = 5,
+                   large_fraction: float = 0.05):
+    """n requests of a Poisson arrival process of the given rate (per second;
+    0 = all arrive at time 0): arrival times (s, ascending) and the pool index
+    each request targets (a large instance with probability large_fraction,
+    else a small one, uniformly within the kind)."""
+    q = np.arange(n)
+    if rate > 0:
+        gaps = -np.log1p(-uniform(seed, _S_ARRIVAL, q)) / rate
+        t = np.cumsum(gaps)
+    else:
+        t = np.zeros(n)
+    large = (uniform(seed, _S_REQ_KIND, q) < large_fraction) & (n_large > 0)
+    if n_small == 0:
+        large[:] = True
+    u = uniform(seed, _S_REQ_PICK, q)
+    small_idx = np.minimum(np.floor(n_small * u).astype(np.int64), max(n_small - 1, 0))
+    large_idx = n_small + np.minimum(np.floor(n_large * u).astype(np.int64), max(n_large - 1, 0))
+    return t, np.where(large, large_idx, small_idx)

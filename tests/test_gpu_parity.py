@@ -68,7 +68,7 @@ def check_cost_table(inst, legs=3, ldc=None):
     return len(mism[0])
 
 
-def test_cost_table_config1():
+def test_cost_table_small_workload():
     assert check_cost_table(synth.workload_instance("small")) == 0
 
 
@@ -128,7 +128,7 @@ def check_scores(C, S, R, ldc=None):
     assert np.array_equal(dist.cpu().numpy(), odist)
 
 
-def test_move_scores_config1_and_2():
+def test_move_scores_small_and_medium():
     for cfg in ("small", "medium"):
         c = synth.WORKLOADS[cfg]
         _, C = instance_and_table(cfg)
@@ -136,14 +136,21 @@ def test_move_scores_config1_and_2():
         check_scores(C, S.tolist(), c["R"])
 
 
-@pytest.mark.parametrize("J,split,U,nt", [(1, 1, 1, 1), (2, 3, 2, 0), (4, 1, 4, 1), (8, 5, 1, 1),
-                                          (1, 7, 4, 0), (2, 1, 4, 1), (4, 2, 2, 1)])
-def test_move_scores_launch_geometries(J, split, U, nt):
+# (rows per workgroup, mission chunks, loads in flight, non-temporal loads,
+#  queued scoring, 1024-thread workgroups)
+GEOMETRIES = [(1, 1, 1, 1, 1, 0), (2, 3, 2, 0, 0, 0), (4, 1, 4, 1, 1, 0), (8, 5, 1, 1, 1, 0),
+              (1, 7, 4, 0, 1, 1), (2, 1, 4, 1, 1, 1), (4, 2, 2, 1, 0, 0), (1, 1, 2, 1, 0, 1),
+              (2, 2, 1, 1, 0, 1)]
+
+
+@pytest.mark.parametrize("J,split,U,nt,q,w", GEOMETRIES)
+def test_move_scores_launch_geometries(J, split, U, nt, q, w):
     inst = synth.make_instance(seed=31, B=90, H=200, M=4103)
     C = oracle_table(inst)
     rng = np.random.default_rng(J * 10 + split)
     S = rng.choice(90, 11, replace=False).tolist()
-    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt):
+    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt,
+             FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w):
         check_scores(C, S, 1_000_000, ldc=4104)   # 16-byte rows
         check_scores(C, S, 1_000_000)             # 4-byte rows (ldc % 4 != 0)
 
@@ -272,9 +279,11 @@ def test_plans_are_bit_identical():
     _, C = instance_and_table("medium")
     Cd = padded_table(C, c["M"])
     ref = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
-    for J, split, U, nt in ((1, 1, 1, 1), (2, 4, 2, 0), (4, 9, 4, 1), (8, 2, 1, 0),
-                            (4, 1, 2, 1), (1, 3, 4, 1)):
-        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt):
+    for J, split, U, nt, q, w in ((1, 1, 1, 1, 1, 0), (2, 4, 2, 0, 0, 0), (4, 9, 4, 1, 1, 0),
+                                  (8, 2, 1, 0, 1, 0), (4, 1, 2, 1, 0, 0), (1, 3, 4, 1, 1, 1),
+                                  (1, 1, 4, 0, 0, 1), (2, 1, 2, 1, 1, 1)):
+        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt,
+                 FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w):
             g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
         assert np.array_equal(g.trace, ref.trace)
         assert np.array_equal(g.best_open.cpu().numpy(), ref.best_open.cpu().numpy())
@@ -312,6 +321,29 @@ def test_full_size_prefix_and_invariants():
     assert g.distance == int(g.trace["best_dist"][-1])
     del Cd
     torch.cuda.empty_cache()
+
+
+def test_built_table_carries_its_mission_count():
+    """build_cost_table returns a (B, M) view of rows padded to a multiple of
+    4; every call that takes it reads M and the pitch from the view, so the
+    padding (uninitialised memory) never counts as missions."""
+    inst = synth.make_instance(seed=41, B=60, H=150, M=1001)
+    C, _ = fs.build_cost_table(to_dev(inst.bases), to_dev(inst.missions))
+    assert tuple(C.shape) == (60, 1001) and C.stride(0) == 1004
+    Ch = C.cpu().numpy()
+    K, R, T, N = 7, 1_100_000, 5, 40
+    g = fs.tabu_solve(C, K, R, T, N)
+    o = oracle.tabu(Ch, K, R, T, N)
+    assert_same_result(g, o, Ch, R)
+    op, _, sums = fs.rank_bases(C, K)
+    assert np.array_equal(op.cpu().numpy(), oracle.rank_bases(Ch, K)[0])
+    assert np.array_equal(sums.cpu().numpy(), Ch.astype(np.int64).sum(axis=1))
+    cov, dist = fs.move_scores(C, op, R)
+    ocov, odist = oracle.move_scores(Ch, oracle.rank_bases(Ch, K)[0], R)
+    assert np.array_equal(cov.cpu().numpy(), ocov) and np.array_equal(dist.cpu().numpy(), odist)
+    b = fs.tabu_solve_batch([dict(C=C, K=K, range_m=R)], T, N)[0]
+    assert np.array_equal(b.best_open.cpu().numpy(), o.best_open)
+    assert (b.coverage, b.distance, b.best_iter) == (o.coverage, o.distance, o.best_iter)
 
 
 def test_invalid_arguments_leave_outputs_untouched():

@@ -315,7 +315,7 @@ def test_tabu_thread_count_invariant():
         assert np.array_equal(getattr(a, f), getattr(b, f))
 
 
-def test_config1_tabu_against_exhaustive_optimum():
+def test_small_workload_tabu_against_exhaustive_optimum():
     """Configuration 1 (40 bases, 200 missions, 5 vehicles, R = 1,200 km): the
     Tabu result never beats the optimum over all C(40,5) = 658,008 placements."""
     c = synth.WORKLOADS["small"]
