@@ -192,11 +192,17 @@ def main():
                    "best_iter": r.best_iter},
     }
     if args.copy_probe:
+        # a plain copy (512 MiB read + 512 MiB written) and a plain read
+        # (512 MiB summed): counter calibration and the streaming rate this
+        # device reaches, beside the sweep's
         x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
-        torch.neg(x, out=y)
+        for _ in range(3):
+            torch.neg(x, out=y)
+            torch.sum(x)
         torch.cuda.synchronize()
-        log("[bench] copy probe: 536870912 B read, 536870912 B written")
+        log("[bench] copy probe: 536870912 B read, 536870912 B written (x3); "
+            "read probe: 536870912 B summed (x3)")
     print(json.dumps(line), flush=True)
 
 

@@ -66,6 +66,9 @@ struct EngineConfig {
     bool nt = true;     // non-temporal row loads
     bool queue = true;  // score only compacted c < b2 elements (wave-level LDS queue)
     bool wide = false;  // 1024-thread sweep workgroups (J <= 2 only)
+    int J_tall = 4;     // rows per workgroup of the sweep_tall tiles
+    int U_tall = 1;
+    int Kmax_tall = 1;  // largest K among the sweep_tall instances
     int Kmax = 1;
 };
 
@@ -75,6 +78,10 @@ struct EngineTables {
     int ninst = 0;
     const Tile *sweep = nullptr;
     int nsweep = 0;
+    // row groups of instances planned with EngineConfig::J_tall rows per
+    // workgroup (tall instances among short ones; never split)
+    const Tile *sweep_tall = nullptr;
+    int nsweep_tall = 0;
     const Tile *score = nullptr;   // row groups of instances with nsplit > 1
     int nscore = 0;
     const Tile *refresh = nullptr;
@@ -84,6 +91,8 @@ struct EngineTables {
 // Geometry of one instance for a given J (rows per workgroup).
 InstPlan plan_instance(int32_t B, int32_t M, int32_t K, int J, int target_wg);
 int choose_rows_per_group(int32_t nclosed, int32_t K);
+// Dynamic LDS of a sweep workgroup of J rows for up to Kmax open slots.
+size_t sweep_lds_of(int J, int Kmax);
 int choose_unroll(int J);
 
 // Workspace layout of one instance.

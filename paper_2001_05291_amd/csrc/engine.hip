@@ -1027,6 +1027,19 @@ __global__ __launch_bounds__(kBlock) void k_assign(const InstDesc *__restrict__ 
 
 // ---------------------------------------------------------------- dispatch
 
+// A launch that carries the timing events when there are any (the dispatch
+// stamps them) and is a plain launch otherwise.
+template <typename... Params, typename... Args>
+void launch_timed(void (*kernel)(Params...), dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                  hipEvent_t start, hipEvent_t stop, Args... args)
+{
+    if (start || stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, s, start, stop, 0u, args...);
+    else
+        kernel<<<grid, block, lds, s>>>(args...);
+}
+
+
 template <int J, int U, bool VEC4, bool NT, bool Q>
 fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
                          TimedLaunch &tm)
@@ -1037,23 +1050,21 @@ fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t s
         bool launched = false;
         if constexpr (J <= 2) {
             if (c.wide) {
-                hipExtLaunchKernelGGL(k_sweep<kWideBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
-                                      dim3(kWideBlock), lds, s, tm.start(),
-                                      score ? nullptr : tm.stop(), 0u, t.desc, t.sweep, step);
+                launch_timed(k_sweep<kWideBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
+                             dim3(kWideBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
+                             t.desc, t.sweep, step);
                 launched = true;
             }
         }
         if (!launched)
-            hipExtLaunchKernelGGL(k_sweep<kBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
-                                  dim3(kBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
-                                  0u, t.desc, t.sweep, step);
+            launch_timed(k_sweep<kBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep), dim3(kBlock), lds,
+                         s, tm.start(), score ? nullptr : tm.stop(), t.desc, t.sweep, step);
         FS_HIP(hipGetLastError());
         if (!score) tm.used();
     }
     if (score) {
-        hipExtLaunchKernelGGL(k_score<J>, dim3(t.nscore), dim3(kBlock), lds, s,
-                              t.nsweep > 0 ? nullptr : tm.start(), tm.stop(), 0u, t.desc, t.score,
-                              step);
+        launch_timed(k_score<J>, dim3(t.nscore), dim3(kBlock), lds, s,
+                     t.nsweep > 0 ? nullptr : tm.start(), tm.stop(), t.desc, t.score, step);
         FS_HIP(hipGetLastError());
         tm.used();
     }
@@ -1091,6 +1102,8 @@ size_t refresh_lds_bytes(int Kmax) { return 16 * (size_t)(Kmax + 1) + 4 * (size_
 }  // namespace
 
 // ---------------------------------------------------------------- planning
+
+size_t sweep_lds_of(int J, int Kmax) { return sweep_lds_bytes(J, Kmax); }
 
 int choose_rows_per_group(int32_t nclosed, int32_t K)
 {
@@ -1247,7 +1260,8 @@ fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step
     return FS_OK;
 }
 
-fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+namespace {
+fs_status sweep_rows(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
     TimedLaunch timed(0);
     switch (c.J) {
@@ -1258,14 +1272,33 @@ fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t ste
     default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
     }
 }
+}  // namespace
+
+fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+{
+    if (t.nsweep > 0 || t.nscore > 0) FS_TRY(sweep_rows(t, c, step, s));
+    if (t.nsweep_tall > 0) {
+        EngineTables tall = t;
+        tall.sweep = t.sweep_tall;
+        tall.nsweep = t.nsweep_tall;
+        tall.score = nullptr;
+        tall.nscore = 0;
+        EngineConfig ct = c;
+        ct.J = c.J_tall;
+        ct.U = c.U_tall;
+        ct.Kmax = c.Kmax_tall;
+        ct.wide = false;
+        FS_TRY(sweep_rows(tall, ct, step, s));
+    }
+    return FS_OK;
+}
 
 fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
     if (t.nrefresh == 0) return FS_OK;
     TimedLaunch timed(1);
-    hipExtLaunchKernelGGL(k_refresh, dim3(t.nrefresh), dim3(kBlock),
-                          (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), 0u,
-                          t.desc, t.refresh, step);
+    launch_timed(k_refresh, dim3(t.nrefresh), dim3(kBlock), (uint32_t)refresh_lds_bytes(c.Kmax), s,
+                 timed.start(), timed.stop(), t.desc, t.refresh, step);
     FS_HIP(hipGetLastError());
     timed.used();
     return FS_OK;

@@ -67,6 +67,7 @@ struct Slot {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     InstDesc desc{};
+    int32_t J = 1;          // rows per sweep workgroup of this request
     int32_t finish_step = 0;
     bool fresh = false;     // admitted this round: initial state still to compute
     bool draining = false;  // finished: results on their way to the host
@@ -345,7 +346,11 @@ fs_status Server::admit(Request *r, int i, bool &admitted)
     FS_HIP(hipMallocAsync(&sl.ws, ws, s));
     sl.ws_bytes = ws;
     used += (int64_t)ws;
-    const InstPlan plan = plan_instance(I.B, I.M, I.K, 1, 0);
+    // tall instances sweep 4 rows per workgroup (fewer re-reads of the
+    // per-mission state); their tiles are launched as a second class
+    int32_t J = (I.B - I.K) >= env_int("FS_SERVE_TALL_ROWS", 1024) ? 4 : 1;
+    if (sweep_lds_of(J, I.K) > ((size_t)56 << 10)) J = 1;
+    const InstPlan plan = plan_instance(I.B, I.M, I.K, J, 0);
     InstDesc d{};
     carve_instance(d, (char *)sl.ws, I.B, I.M, I.K, plan);
     d.C = I.C;
@@ -369,6 +374,7 @@ fs_status Server::admit(Request *r, int i, bool &admitted)
         if (!closed.empty()) FS_TRY(upload(d.closed[1], closed.data(), 4 * closed.size()));
     }
     sl.desc = d;
+    sl.J = J;
     sl.req = r;
     sl.inst = &I;
     sl.fresh = true;
@@ -458,8 +464,8 @@ void Server::retire(int i, fs_status st, const char *msg)
 fs_status Server::rebuild_tables()
 {
     std::vector<InstDesc> descs(slots.size(), InstDesc{});
-    std::vector<Tile> sweep, refresh;
-    int32_t Kmax = 1;
+    std::vector<Tile> sweep, tall, refresh;
+    int32_t Kmax = 1, Kmax_tall = 1;
     size_t table_bytes = 0;
     for (size_t i = 0; i < slots.size(); ++i) {
         const Slot &sl = slots[i];
@@ -469,15 +475,16 @@ fs_status Server::rebuild_tables()
         const InstDesc &d = sl.desc;
         Kmax = std::max(Kmax, d.K);
         table_bytes += (size_t)d.B * d.M * 4;
+        if (sl.J == 4) Kmax_tall = std::max(Kmax_tall, d.K);
         for (int32_t g = 0; g < std::max(d.ngroups, 1); ++g)
-            sweep.push_back(Tile{(int32_t)i, g, 0, 0});
+            (sl.J == 4 ? tall : sweep).push_back(Tile{(int32_t)i, g, 0, 0});
         for (int32_t g = 0; g < (d.Mp + kRefreshMissions - 1) / kRefreshMissions; ++g)
             refresh.push_back(Tile{(int32_t)i, g, 0, 0});
     }
     FS_TRY(upload(d_desc, descs.data(), sizeof(InstDesc) * descs.size()));
     // the tables stay until the set of running slots changes; a copy into
     // them is stream-ordered after every kernel that read the old contents
-    const size_t ntiles = sweep.size() + refresh.size();
+    const size_t ntiles = sweep.size() + tall.size() + refresh.size();
     if (ntiles > tiles_cap) {
         const size_t cap = std::max(ntiles, 2 * tiles_cap);
         Tile *fresh = nullptr;
@@ -486,15 +493,20 @@ fs_status Server::rebuild_tables()
         d_tiles = fresh;
         tiles_cap = cap;
     }
+    const size_t nshort = sweep.size(), ntall = tall.size();
+    sweep.insert(sweep.end(), tall.begin(), tall.end());
     sweep.insert(sweep.end(), refresh.begin(), refresh.end());
     FS_TRY(upload(d_tiles, sweep.data(), sizeof(Tile) * ntiles));
     tabs.sweep = d_tiles;
-    tabs.nsweep = (int)(ntiles - refresh.size());
-    tabs.refresh = d_tiles + tabs.nsweep;
+    tabs.nsweep = (int)nshort;
+    tabs.sweep_tall = d_tiles + nshort;
+    tabs.nsweep_tall = (int)ntall;
+    tabs.refresh = d_tiles + nshort + ntall;
     tabs.nrefresh = (int)refresh.size();
     tabs.score = nullptr;
     tabs.nscore = 0;
     ecfg.Kmax = Kmax;
+    ecfg.Kmax_tall = Kmax_tall;
     ecfg.nt = table_bytes > ((size_t)96 << 20);
     tiles_dirty = false;
     return FS_OK;

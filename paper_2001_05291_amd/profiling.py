@@ -53,18 +53,33 @@ def counter_per_dispatch(db: str, kernel_re: str, counter: str):
         "select name, dispatch_id, sum(counter_value) from pmc_events where counter_name = ? "
         "group by dispatch_id, name", (counter,)).fetchall()
     con.close()
-    vals = [v for n, _, v in rows if re.search(kernel_re, short_name(n or ""))]
-    if not vals:
+    hits = [(short_name(n or ""), v) for n, _, v in rows
+            if re.search(kernel_re, short_name(n or ""))]
+    if not hits:
         raise SystemExit(f"no {counter} samples for kernels matching {kernel_re!r} in {db}")
+    names = sorted({n for n, _ in hits})
+    if len(names) > 1:
+        raise SystemExit(f"{kernel_re!r} matches several kernels in {db}: {names}")
+    vals = [v for _, v in hits]
     return statistics.fmean(vals), len(vals)
 
 
-def write_trace(db: str, out: str, title: str, command: str):
+def write_trace(db: str, out: str, title: str, command: str, copy_re: str | None = None,
+                copy_bytes: int = 0):
     lines = [f"# {title}", "", "Command:", "", "```", command, "```", "",
              "| kernel | calls | mean (us) | min (us) | max (us) | total (ms) |",
              "|---|---:|---:|---:|---:|---:|"]
-    for n, c, a, lo, hi, s in kernel_stats(db):
+    stats = kernel_stats(db)
+    for n, c, a, lo, hi, s in stats:
         lines.append(f"| `{n}` | {c} | {a:.2f} | {lo:.2f} | {hi:.2f} | {s:.3f} |")
+    if copy_re:
+        hits = [x for x in stats if re.search(copy_re, x[0])]
+        if len(hits) != 1:
+            raise SystemExit(f"{copy_re!r} must match exactly one kernel, got {[h[0] for h in hits]}")
+        n, c, a, lo, hi, _ = hits[0]
+        lines += ["", f"Plain device copy (`{copy_re}`, {copy_bytes} B read + written): "
+                      f"{lo:.1f} us at best -> {copy_bytes / (lo * 1e-6) / 1e9:.0f} GB/s "
+                      "(the HBM rate a streaming kernel reaches on this device)"]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -118,6 +133,8 @@ def main():
     t.add_argument("out")
     t.add_argument("--title", required=True)
     t.add_argument("--command", required=True)
+    t.add_argument("--copy", default=None, help="kernel-name regex of the copy probe")
+    t.add_argument("--copy-bytes", type=int, default=0, help="bytes it reads plus writes")
     r = sub.add_parser("traffic")
     r.add_argument("out")
     r.add_argument("--fetch", required=True)
@@ -130,7 +147,7 @@ def main():
     r.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
     if a.cmd == "trace":
-        write_trace(a.db, a.out, a.title, a.command)
+        write_trace(a.db, a.out, a.title, a.command, a.copy, a.copy_bytes)
     else:
         write_traffic(a.fetch, a.write, a.kernel, a.copy, a.copy_bytes, a.algorithmic_bytes,
                       a.out, a.command, a.workload)

@@ -84,6 +84,19 @@ def test_served_equals_plain(fs, slots):
     assert all(s.latency_s > 0 for s in served)
 
 
+def test_tall_and_short_instances_in_one_round(fs, monkeypatch):
+    """Instances with many closed bases are swept four rows per workgroup as a
+    second tile class in the same rounds as the others (threshold lowered so
+    that the small test instances fall on both sides of it)."""
+    monkeypatch.setenv("FS_SERVE_TALL_ROWS", "60")
+    insts, reqs = make_workload(6, 24, seed=7)
+    assert any(w["inst"].B - w["K"] >= 60 for w in insts)
+    assert any(w["inst"].B - w["K"] < 60 for w in insts)
+    plain = plain_replay(fs, insts, reqs, T=5, N=30)
+    served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
+    assert_same(served, plain)
+
+
 def test_local_search_requests(fs):
     insts, reqs = make_workload(3, 9, seed=2)
     plain = plain_replay(fs, insts, reqs, T=5, N=25, mode=1)
