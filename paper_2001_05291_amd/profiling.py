@@ -45,9 +45,11 @@ def kernel_stats(db: str):
     return [(short_name(n), c, a / 1e3, lo / 1e3, hi / 1e3, s / 1e6) for n, c, a, lo, hi, s in rows]
 
 
-def counter_per_dispatch(db: str, kernel_re: str, counter: str):
-    """Mean over dispatches of kernels matching kernel_re of the counter's value
-    summed over its instances; also the number of dispatches."""
+def counter_per_dispatch(db: str, kernel_re: str, counter: str, most_used: bool = False):
+    """Mean over dispatches of the kernel matching kernel_re of the counter's
+    value summed over its instances; also the number of dispatches.  Several
+    matching kernels are an error unless most_used, which takes the one
+    dispatched most often (the variant the autotuner kept, not its trials)."""
     con = sqlite3.connect(db)
     rows = con.execute(
         "select name, dispatch_id, sum(counter_value) from pmc_events where counter_name = ? "
@@ -59,9 +61,22 @@ def counter_per_dispatch(db: str, kernel_re: str, counter: str):
         raise SystemExit(f"no {counter} samples for kernels matching {kernel_re!r} in {db}")
     names = sorted({n for n, _ in hits})
     if len(names) > 1:
-        raise SystemExit(f"{kernel_re!r} matches several kernels in {db}: {names}")
+        if not most_used:
+            raise SystemExit(f"{kernel_re!r} matches several kernels in {db}: {names}")
+        top = max(names, key=lambda x: sum(1 for n, _ in hits if n == x))
+        hits = [(n, v) for n, v in hits if n == top]
     vals = [v for _, v in hits]
     return statistics.fmean(vals), len(vals)
+
+
+def kernel_name(db: str, kernel_re: str, counter: str) -> str:
+    """Name of the most-dispatched kernel matching kernel_re in a counter run."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name from pmc_events where counter_name = ? group by dispatch_id, "
+                       "name", (counter,)).fetchall()
+    con.close()
+    names = [short_name(n or "") for (n,) in rows if re.search(kernel_re, short_name(n or ""))]
+    return max(set(names), key=names.count)
 
 
 def write_trace(db: str, out: str, title: str, command: str, copy_re: str | None = None,
@@ -86,8 +101,9 @@ def write_trace(db: str, out: str, title: str, command: str, copy_re: str | None
 
 def write_traffic(fetch_db: str, write_db: str, kernel_re: str, copy_re: str, copy_bytes: int,
                   algorithmic: int, out: str, commands, workload: str):
-    f_k, n_f = counter_per_dispatch(fetch_db, kernel_re, "FETCH_SIZE")
-    w_k, n_w = counter_per_dispatch(write_db, kernel_re, "WRITE_SIZE")
+    f_k, n_f = counter_per_dispatch(fetch_db, kernel_re, "FETCH_SIZE", most_used=True)
+    w_k, n_w = counter_per_dispatch(write_db, kernel_re, "WRITE_SIZE", most_used=True)
+    used = kernel_name(fetch_db, kernel_re, "FETCH_SIZE")
     f_c, _ = counter_per_dispatch(fetch_db, copy_re, "FETCH_SIZE")
     w_c, _ = counter_per_dispatch(write_db, copy_re, "WRITE_SIZE")
     f_scale = copy_bytes / (f_c * 1024.0)
@@ -97,6 +113,7 @@ def write_traffic(fetch_db: str, write_db: str, kernel_re: str, copy_re: str, co
     total = fetch_b + write_b
     lines = [f"# HBM traffic of `{kernel_re}` ({workload})", "",
              "Commands:", "", "```", *commands, "```", "",
+             f"- kernel measured: `{used}` (the most-dispatched match)",
              f"- FETCH_SIZE per dispatch: {f_k:.1f} KiB over {n_f} dispatches; copy kernel "
              f"(`{copy_re}`, {copy_bytes} B read): {f_c:.1f} KiB -> scale {f_scale:.4f}",
              f"- WRITE_SIZE per dispatch: {w_k:.1f} KiB over {n_w} dispatches; copy kernel "
