@@ -12,11 +12,13 @@ constexpr int kRefreshMissions = 64; // missions per refresh workgroup (one per 
 
 // Everything one instance's kernels need; lives in device memory.
 //
-// Iteration t (1-based) of an instance works on placement S_t.  Buffers that
-// one iteration reads while the next is being prepared are double-buffered by
-// the parity of t: open/closed lists and the G/L accumulators of S_t live in
-// slot (t & 1).  The iteration number of an instance is the launch step minus
-// start_step.
+// Iteration t (1-based) of an instance works on placement S_t.  The G/L
+// accumulators of S_t live in slot (t & 1) (the refresh of iteration t fills
+// those of S_{t+1} while the scores of S_t are still being read).  The open
+// and closed lists are single: a move changes one slot of each, which the
+// refresh's first workgroup writes in place (any other workgroup of that
+// refresh that reads the open list patches the same slot to the same value).
+// The iteration number of an instance is the launch step minus start_step.
 struct InstDesc {
     const int32_t *C;
     int64_t ldc;
@@ -24,9 +26,11 @@ struct InstDesc {
     int32_t nclosed, chunk, nsplit, ngroups;
     int32_t active;          // 0: every kernel skips this instance
     int32_t start_step;      // launch step at which this instance's iteration 0 ends
-    int32_t *open[2];        // K      slot -> base id
-    int32_t *closed[2];      // B - K  slot -> base id (at least one entry)
-    int32_t *tabu_until;     // B
+    int32_t *open;           // K      slot -> base id
+    int32_t *closed;         // B - K  slot -> base id (at least one entry)
+    int32_t *open_tabu;      // K      slot -> last iteration its base is tabu
+    int32_t *closed_tabu;    // B - K  (kept beside the lists so that no kernel
+                             //        has to look a base's tabu state up by id)
     int32_t *b1, *b2, *o1;   // Mp: nearest open cost, second-nearest, nearest slot
     Acc *acc[2];             // kStripes x (K + 1): G at [s][0], L_k at [s][1 + k]
     Candidate *cand;         // max(ngroups, 1): best admissible move per row group
@@ -65,7 +69,8 @@ struct EngineConfig {
     bool vec4 = true;   // 16-byte row loads (all tables 16-byte aligned, ldc % 4 == 0)
     bool nt = true;     // non-temporal row loads
     bool queue = true;  // score only compacted c < b2 elements (wave-level LDS queue)
-    bool wide = false;  // 1024-thread sweep workgroups (J <= 2 only)
+    bool wide = false;  // 1024-thread sweep workgroups (J <= 2, or in-place
+                        // scoring with U = 1)
     int J_tall = 4;     // rows per workgroup of the sweep_tall tiles
     int U_tall = 1;
     int Kmax_tall = 1;  // largest K among the sweep_tall instances
@@ -90,7 +95,9 @@ struct EngineTables {
 
 // Geometry of one instance for a given J (rows per workgroup).
 InstPlan plan_instance(int32_t B, int32_t M, int32_t K, int J, int target_wg);
-int choose_rows_per_group(int32_t nclosed, int32_t K);
+// Rows per sweep workgroup from the median instance's closed rows and
+// missions and the launch set's total closed rows.
+int choose_rows_per_group(int32_t nclosed, int32_t M, int64_t total_rows, int32_t K);
 // Dynamic LDS of a sweep workgroup of J rows for up to Kmax open slots.
 size_t sweep_lds_of(int J, int Kmax);
 int choose_unroll(int J);

@@ -156,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_reset(const InstDesc *__restrict__ d
     const InstDesc &d = descs[inst];
     if (!d.active) return;
     const int32_t q = blk * kBlock + threadIdx.x;
-    if (q < d.B) d.tabu_until[q] = 0;
+    if (q < d.K) d.open_tabu[q] = 0;
+    if (q < max(d.nclosed, 1)) d.closed_tabu[q] = 0;
     if (q < kStripes * (d.K + 1)) {
         d.acc[0][q].cov = 0;
         d.acc[0][q].dist = 0;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restric
     }
     __syncthreads();
     int32_t before = s_cnt[threadIdx.x];
-    int32_t *op = d.open[1], *cl = d.closed[1];
+    int32_t *op = d.open, *cl = d.closed;
     for (int32_t b = lo; b < hi; ++b) {
         if (sel[b]) {
             op[before] = b;
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             const Candidate c = d.cand[q];
             if (cand_better(c, best)) best = c;
         }
-        const int32_t *cur_open = d.open[t & 1];
+        const int32_t *cur_open = d.open;
         for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = cur_open[k];
         best = block_best(best, s_red);   // barriers: s_open complete too
         if (!best.valid && d.mode == 1) {
@@ -327,8 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                 SolveState s = *st;
                 int32_t improved = 0;
                 if (best.valid) {
-                    d.tabu_until[best.i_base] = t + d.T;
-                    d.tabu_until[best.j_base] = t + d.T;
                     s.cur_cov = best.cov;
                     s.cur_dist = best.dist;
                     if (better(best.cov, best.dist, s.best_cov, s.best_dist)) {
@@ -343,21 +342,22 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                 s_improved = improved;
             }
             __syncthreads();
-            int32_t *nxt_open = d.open[(t + 1) & 1];
-            int32_t *nxt_closed = d.closed[(t + 1) & 1];
-            const int32_t *cur_closed = d.closed[t & 1];
-            for (int k = threadIdx.x; k < K; k += kBlock) {
-                const int32_t v = (best.valid && k == best.i_slot) ? best.j_base : s_open[k];
-                nxt_open[k] = v;
-                if (s_improved) d.best_open[k] = v;
+            // the swap: the two bases trade list slots, and both stay tabu
+            // through iteration t + T (the expiry travels with the base)
+            if (best.valid && threadIdx.x == 0) {
+                d.open[best.i_slot] = best.j_base;
+                d.open_tabu[best.i_slot] = t + d.T;
+                d.closed[best.j_slot] = best.i_base;
+                d.closed_tabu[best.j_slot] = t + d.T;
             }
-            for (int32_t q = threadIdx.x; q < d.nclosed; q += kBlock)
-                nxt_closed[q] = (best.valid && q == best.j_slot) ? best.i_base : cur_closed[q];
+            if (s_improved)
+                for (int k = threadIdx.x; k < K; k += kBlock)
+                    d.best_open[k] = (best.valid && k == best.i_slot) ? best.j_base : s_open[k];
         }
         __syncthreads();
         if (best.valid && threadIdx.x == 0) s_open[best.i_slot] = best.j_base;
     } else {
-        const int32_t *first = d.open[1];
+        const int32_t *first = d.open;
         for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = first[k];
     }
     for (int k = threadIdx.x; k <= K; k += kBlock) {
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restric
         s.best_dist = gd;
         *d.st = s;
     }
-    for (int k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[1][k];
+    for (int k = threadIdx.x; k < d.K; k += kBlock) d.best_open[k] = d.open[k];
 }
 
 // ---------------------------------------------------------------- sweep (A3, A4 local)
@@ -510,7 +510,7 @@ struct SweepLds {
     int32_t *bc;    // J*K bins: coverage
     int32_t *Lc;    // K+1: G, L_k coverage
     int32_t *open;  // K: open base of each slot
-    int32_t *otabu; // K: tabu_until of each open base
+    int32_t *otabu; // K: tabu expiry of each open slot
 };
 
 __device__ __forceinline__ SweepLds carve_lds(unsigned char *smem, int J, int K)
@@ -532,7 +532,8 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
 {
     const int32_t K = d.K;
     const Acc *acc = d.acc[t & 1];
-    const int32_t *op = d.open[t & 1];
+    const int32_t *op = d.open;
+    const int32_t *ot = d.open_tabu;
     for (int32_t k = threadIdx.x; k <= K; k += blockDim.x) {
         int32_t c;
         int64_t dd;
@@ -540,9 +541,8 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
         L.Lc[k] = c;
         L.Ld[k] = dd;
         if (k < K) {
-            const int32_t id = op[k];
-            L.open[k] = id;
-            L.otabu[k] = d.tabu_until[id];
+            L.open[k] = op[k];
+            L.otabu[k] = ot[k];
         }
     }
 }
@@ -550,15 +550,19 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
 // Scores of the J x K moves of row group g from the per-row common sums
 // (t1c, t1d) and the per-(row, out-slot) bins; writes the optional full score
 // table and the group's best admissible candidate.
+// Called by every thread of the workgroup.  st: the search state (read at
+// kernel start).  When the group has at most 64 moves the first wave scores
+// them alone and the rest of the workgroup may leave.
 template <int BS>
-__device__ void score_group(const InstDesc &d, int J, int32_t t, int32_t g,
+__device__ void score_group(const InstDesc &d, const SolveState &st, int J, int32_t t, int32_t g,
                             const int32_t *s_jrow, const int32_t *s_jtabu, const SweepLds &L,
                             const int32_t *t1c, const int64_t *t1d, Candidate *s_red)
 {
     const int32_t K = d.K;
-    const SolveState *st = d.st;
-    const int32_t cur_c = st->cur_cov, best_c = st->best_cov;
-    const int64_t cur_d = st->cur_dist, best_d = st->best_dist;
+    const bool one_wave = J * K <= 64;
+    if (one_wave && threadIdx.x >= 64) return;
+    const int32_t cur_c = st.cur_cov, best_c = st.best_cov;
+    const int64_t cur_d = st.cur_dist, best_d = st.best_dist;
     const int32_t Gc = L.Lc[0];
     const int64_t Gd = L.Ld[0];
     Candidate mine{};
@@ -590,7 +594,15 @@ __device__ void score_group(const InstDesc &d, int J, int32_t t, int32_t g,
             if (cand_better(c, mine)) mine = c;
         }
     }
-    mine = block_best<BS>(mine, s_red);
+    if (one_wave) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const Candidate o = shfl_xor_cand(mine, off);
+            if (cand_better(o, mine)) mine = o;
+        }
+    } else {
+        mine = block_best<BS>(mine, s_red);
+    }
     if (threadIdx.x == 0) d.cand[g] = mine;
 }
 
@@ -844,7 +856,9 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
-    if (t < 1 || t > d.N || d.st->stopped) return;
+    if (t < 1 || t > d.N) return;
+    const SolveState st = *d.st;
+    if (st.stopped) return;
     const bool scoring = d.nsplit == 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K;
@@ -864,9 +878,9 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     const int32_t nclosed = d.nclosed;
     if (threadIdx.x < J) {
         const int32_t js = tl.g * J + threadIdx.x;
-        const int32_t j = nclosed > 0 ? d.closed[t & 1][js < nclosed ? js : 0] : 0;
-        s_jrow[threadIdx.x] = j;
-        if (scoring) s_jtabu[threadIdx.x] = d.tabu_until[j];
+        const int32_t jc = js < nclosed ? js : 0;
+        s_jrow[threadIdx.x] = nclosed > 0 ? d.closed[jc] : 0;
+        if (scoring) s_jtabu[threadIdx.x] = nclosed > 0 ? d.closed_tabu[jc] : 0;
     }
     if (scoring) load_slot_inputs(d, t, L);
     __syncthreads();
@@ -894,7 +908,7 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     reduce_rows<BS, J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
 
     if (scoring) {
-        score_group<BS>(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
+        score_group<BS>(d, st, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
     } else {
         // partial sums of this chunk: [T1, bin_0 .. bin_{K-1}] per row
         const int32_t K1 = K + 1;
@@ -923,7 +937,9 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
-    if (t < 1 || t > d.N || d.st->stopped) return;
+    if (t < 1 || t > d.N) return;
+    const SolveState st = *d.st;
+    if (st.stopped) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K, K1 = K + 1;
     const SweepLds L = carve_lds(smem, J, K);
@@ -934,9 +950,9 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
     const int32_t nclosed = d.nclosed;
     if (threadIdx.x < J) {
         const int32_t js = tl.g * J + threadIdx.x;
-        const int32_t j = d.closed[t & 1][js < nclosed ? js : 0];
-        s_jrow[threadIdx.x] = j;
-        s_jtabu[threadIdx.x] = d.tabu_until[j];
+        const int32_t jc = js < nclosed ? js : 0;
+        s_jrow[threadIdx.x] = d.closed[jc];
+        s_jtabu[threadIdx.x] = d.closed_tabu[jc];
     }
     load_slot_inputs(d, t, L);
     for (int32_t idx = threadIdx.x; idx < J * K1; idx += kBlock) {
@@ -960,7 +976,7 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
         }
     }
     __syncthreads();
-    score_group<kBlock>(d, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
+    score_group<kBlock>(d, st, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
 }
 
 // ---------------------------------------------------------------- outputs
@@ -1048,7 +1064,10 @@ fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t s
     const bool score = t.nscore > 0;
     if (t.nsweep > 0) {
         bool launched = false;
-        if constexpr (J <= 2) {
+        // 1024-thread workgroups: up to 2 rows with any variant; more rows
+        // only with in-place scoring and one load in flight (LDS queues and
+        // registers grow with the rows)
+        if constexpr (J <= 2 || (!Q && U == 1)) {
             if (c.wide) {
                 launch_timed(k_sweep<kWideBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
                              dim3(kWideBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
@@ -1105,10 +1124,13 @@ size_t refresh_lds_bytes(int Kmax) { return 16 * (size_t)(Kmax + 1) + 4 * (size_
 
 size_t sweep_lds_of(int J, int Kmax) { return sweep_lds_bytes(J, Kmax); }
 
-int choose_rows_per_group(int32_t nclosed, int32_t K)
+int choose_rows_per_group(int32_t nclosed, int32_t M, int64_t total_rows, int32_t K)
 {
+    // many rows: fewer re-reads of the per-mission state per row; short rows
+    // (a few thousand missions) in a launch with rows to spare: enough
+    // streaming per workgroup to hide its fixed start-up and scoring latency
     int J = 1;
-    if (nclosed >= 2048)
+    if (nclosed >= 2048 || (M < 8192 && nclosed >= 16 && total_rows >= 8192))
         J = 4;
     else if (nclosed >= 1024)
         J = 2;
@@ -1152,9 +1174,10 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
     const size_t Mp = (size_t)(M + 3) / 4 * 4;
     const size_t nclosed = (size_t)std::max(p.nclosed, 1);
     size_t n = 0;
-    n += 2 * align_up(4 * (size_t)K, 256);                      // open lists
-    n += 2 * align_up(4 * nclosed, 256);                        // closed lists
-    n += align_up(4 * (size_t)B, 256);                          // tabu_until
+    n += align_up(4 * (size_t)K, 256);                          // open list
+    n += align_up(4 * nclosed, 256);                            // closed list
+    n += align_up(4 * (size_t)K, 256);                          // open tabu expiries
+    n += align_up(4 * nclosed, 256);                            // closed tabu expiries
     n += 3 * align_up(4 * Mp, 256);                             // b1 b2 o1
     n += 2 * align_up(sizeof(Acc) * kStripes * (K + 1), 256);   // accumulators
     n += align_up(sizeof(Candidate) * std::max(p.ngroups, 1), 256);
@@ -1177,11 +1200,10 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
         q += align_up(bytes, 256);
         return r;
     };
-    d.open[0] = (int32_t *)take(4 * (size_t)K);
-    d.open[1] = (int32_t *)take(4 * (size_t)K);
-    d.closed[0] = (int32_t *)take(4 * nclosed);
-    d.closed[1] = (int32_t *)take(4 * nclosed);
-    d.tabu_until = (int32_t *)take(4 * (size_t)B);
+    d.open = (int32_t *)take(4 * (size_t)K);
+    d.closed = (int32_t *)take(4 * nclosed);
+    d.open_tabu = (int32_t *)take(4 * (size_t)K);
+    d.closed_tabu = (int32_t *)take(4 * nclosed);
     d.b1 = (int32_t *)take(4 * Mp);
     d.b2 = (int32_t *)take(4 * Mp);
     d.o1 = (int32_t *)take(4 * Mp);

@@ -37,10 +37,14 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
         Bmax = std::max(Bmax, p.B);
         vec4 = vec4 && (p.ldc % 4 == 0) && ((uintptr_t)p.C % 16 == 0);
     }
-    std::vector<int32_t> sorted_ncl = ncl;
+    std::vector<int32_t> sorted_ncl = ncl, sorted_m(n);
+    for (int i = 0; i < n; ++i) sorted_m[i] = specs[i].M;
     std::sort(sorted_ncl.begin(), sorted_ncl.end());
+    std::sort(sorted_m.begin(), sorted_m.end());
     EngineConfig &cfg = ls.cfg;
-    cfg.J = choose_rows_per_group(sorted_ncl[n / 2], Kmax);
+    int64_t total_rows = 0;
+    for (int32_t c : ncl) total_rows += c;
+    cfg.J = choose_rows_per_group(sorted_ncl[n / 2], sorted_m[n / 2], total_rows, Kmax);
     cfg.U = choose_unroll(cfg.J);
     cfg.vec4 = vec4;
     // non-temporal row loads once the tables outgrow what the 256 MB
@@ -124,10 +128,10 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
             d.sums = nullptr;
             // lists of S_1 (parity 1): open list as given, closed list = the
             // complement in ascending id order
-            d.open[1] = lists_dev + lpos;
+            d.open = lists_dev + lpos;
             memcpy(lists_host + lpos, p.init_host, 4 * (size_t)p.K);
             lpos += p.K;
-            d.closed[1] = lists_dev + lpos;
+            d.closed = lists_dev + lpos;
             std::vector<unsigned char> in(p.B, 0);
             for (int32_t k = 0; k < p.K; ++k) in[p.init_host[k]] = 1;
             size_t c = 0;
@@ -224,7 +228,8 @@ fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
     std::vector<EngineConfig> cands;
     for (int U : {1, 2, 4})
         for (int q = 0; q < 2; ++q)
-            for (int w = 0; w < (ls.cfg.J <= 2 ? 2 : 1); ++w) {
+            for (int w = 0; w < 2; ++w) {
+                if (w && ls.cfg.J > 2 && (q || U != 1)) continue;   // no such wide form
                 EngineConfig c = ls.cfg;
                 c.U = U;
                 c.queue = q != 0;

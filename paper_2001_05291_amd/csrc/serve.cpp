@@ -346,9 +346,11 @@ fs_status Server::admit(Request *r, int i, bool &admitted)
     FS_HIP(hipMallocAsync(&sl.ws, ws, s));
     sl.ws_bytes = ws;
     used += (int64_t)ws;
-    // tall instances sweep 4 rows per workgroup (fewer re-reads of the
-    // per-mission state); their tiles are launched as a second class
-    int32_t J = (I.B - I.K) >= env_int("FS_SERVE_TALL_ROWS", 1024) ? 4 : 1;
+    // instances with many rows, or short rows, sweep 4 rows per workgroup
+    // (fewer re-reads of the per-mission state; enough streaming per
+    // workgroup); their tiles are launched as a second class
+    const int32_t ncl = I.B - I.K;
+    int32_t J = (ncl >= env_int("FS_SERVE_TALL_ROWS", 1024) || (I.M < 8192 && ncl >= 16)) ? 4 : 1;
     if (sweep_lds_of(J, I.K) > ((size_t)56 << 10)) J = 1;
     const InstPlan plan = plan_instance(I.B, I.M, I.K, J, 0);
     InstDesc d{};
@@ -370,8 +372,8 @@ fs_status Server::admit(Request *r, int i, bool &admitted)
         for (int32_t b : I.last_best) in[b] = 1;
         for (int32_t b = 0; b < I.B; ++b)
             if (!in[b]) closed.push_back(b);
-        FS_TRY(upload(d.open[1], I.last_best.data(), 4 * (size_t)I.K));
-        if (!closed.empty()) FS_TRY(upload(d.closed[1], closed.data(), 4 * closed.size()));
+        FS_TRY(upload(d.open, I.last_best.data(), 4 * (size_t)I.K));
+        if (!closed.empty()) FS_TRY(upload(d.closed, closed.data(), 4 * closed.size()));
     }
     sl.desc = d;
     sl.J = J;

@@ -84,15 +84,18 @@ def test_served_equals_plain(fs, slots):
     assert all(s.latency_s > 0 for s in served)
 
 
-def test_tall_and_short_instances_in_one_round(fs, monkeypatch):
-    """Instances with many closed bases are swept four rows per workgroup as a
-    second tile class in the same rounds as the others (threshold lowered so
-    that the small test instances fall on both sides of it)."""
-    monkeypatch.setenv("FS_SERVE_TALL_ROWS", "60")
-    insts, reqs = make_workload(6, 24, seed=7)
-    assert any(w["inst"].B - w["K"] >= 60 for w in insts)
-    assert any(w["inst"].B - w["K"] < 60 for w in insts)
+def test_two_sweep_classes_in_one_round(fs, monkeypatch):
+    """Instances with at least 16 closed bases and short rows are swept four
+    rows per workgroup, the others one row per workgroup, as two tile classes
+    in the same rounds; then again with the many-rows threshold lowered so the
+    rule's other branch is taken too."""
+    insts, reqs = make_workload(8, 32, seed=7, sizes=((8, 60), (100, 1500), (2, 12)))
+    ncl = [w["inst"].B - w["K"] for w in insts]
+    assert any(n >= 16 for n in ncl) and any(n < 16 for n in ncl)
     plain = plain_replay(fs, insts, reqs, T=5, N=30)
+    served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
+    assert_same(served, plain)
+    monkeypatch.setenv("FS_SERVE_TALL_ROWS", "10")
     served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
     assert_same(served, plain)
 
