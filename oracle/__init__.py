@@ -81,6 +81,25 @@ def _load():
     lib.fso_brute_optimum.argtypes = [_i32p, i64, i32, i32, i32, i32, _i32p,
                                       _c.POINTER(i32), _c.POINTER(i64), _c.POINTER(i64)]
     lib.fso_brute_optimum.restype = None
+    lib.fso_fleet_value.argtypes = [_i32p, i64, i32, _i32p, _i32p, i32, _i32p, i32,
+                                    _c.POINTER(i32), _c.POINTER(i64)]
+    lib.fso_fleet_value.restype = None
+    lib.fso_fleet_assign.argtypes = [_i32p, i64, i32, _i32p, _i32p, i32, _i32p, i32, _i32p]
+    lib.fso_fleet_assign.restype = None
+    lib.fso_fleet_move_scores.argtypes = [_i32p, i64, i32, i32, _i32p, _i32p, i32, _i32p,
+                                          _i32p, i32, _i32p, _i64p]
+    lib.fso_fleet_move_scores.restype = None
+    lib.fso_fleet_rank.argtypes = [_i32p, i64, i32, i32, i32, i32, _i32p, _i32p, _i32p]
+    lib.fso_fleet_rank.restype = _c.c_int
+    lib.fso_fleet_tabu.argtypes = [_i32p, i64, i32, i32, i32, i32, _i32p, _i32p, i32, i32, i32,
+                                   i32, n_i32, n_i32, _i32p, _i32p, _c.POINTER(i32),
+                                   _c.POINTER(i64), _c.POINTER(i32), n_i32, n_i32, n_i32, n_i32,
+                                   n_i64, n_i32, n_i64]
+    lib.fso_fleet_tabu.restype = _c.c_int
+    lib.fso_fleet_brute_optimum.argtypes = [_i32p, i64, i32, i32, i32, i32, _i32p, _i32p, i32,
+                                            _i32p, _i32p, _c.POINTER(i32), _c.POINTER(i64),
+                                            _c.POINTER(i64)]
+    lib.fso_fleet_brute_optimum.restype = None
     _lib = lib
     return lib
 
@@ -219,3 +238,106 @@ def brute_optimum(C, K: int, R: int, M: int | None = None):
     _load().fso_brute_optimum(C, ldc, B, M, int(K), int(R), best, _c.byref(cov),
                               _c.byref(dist), _c.byref(n))
     return best, int(cov.value), int(dist.value), int(n.value)
+
+
+# ---------------------------------------------------------------- heterogeneous fleet
+# (Section 3, Eq. 2-10; readings in fleet_oracle.c)
+
+def _flags(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(-1))
+    if a.shape[0] != n:
+        raise ValueError(f"expected {n} flags, got {a.shape[0]}")
+    return a
+
+
+def fleet_value(C, S, rot, rotary_only, R: int):
+    C, B, M = _cm(C)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    rot = _flags(rot, S.shape[0])
+    cov = _c.c_int32()
+    dist = _c.c_int64()
+    _load().fso_fleet_value(C, M, M, S, rot, S.shape[0], _flags(rotary_only, M), int(R),
+                            _c.byref(cov), _c.byref(dist))
+    return int(cov.value), int(dist.value)
+
+
+def fleet_assign(C, S, rot, rotary_only, R: int):
+    C, B, M = _cm(C)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    out = np.zeros(M, dtype=np.int32)
+    _load().fso_fleet_assign(C, M, M, S, _flags(rot, S.shape[0]), S.shape[0],
+                             _flags(rotary_only, M), int(R), out)
+    return out
+
+
+def fleet_move_scores(C, S, rot, heliport, rotary_only, R: int):
+    """(cov K x B, dist K x B) of every relocation; -1 where not a move."""
+    C, B, M = _cm(C)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    K = S.shape[0]
+    cov = np.zeros((K, B), dtype=np.int32)
+    dist = np.zeros((K, B), dtype=np.int64)
+    _load().fso_fleet_move_scores(C, M, B, M, S, _flags(rot, K), K, _flags(heliport, B),
+                                  _flags(rotary_only, M), int(R), cov, dist)
+    return cov, dist
+
+
+def fleet_rank(C, K_r: int, K_f: int, heliport):
+    """(bases, rotary flags) in slot order; raises when the bases cannot hold the fleet."""
+    C, B, M = _cm(C)
+    K = int(K_r) + int(K_f)
+    op = np.zeros(max(K, 1), dtype=np.int32)
+    rot = np.zeros(max(K, 1), dtype=np.int32)
+    if _load().fso_fleet_rank(C, M, B, M, int(K_r), int(K_f), _flags(heliport, B), op, rot):
+        raise ValueError("the bases cannot hold the fleet")
+    return op[:K], rot[:K]
+
+
+@dataclass
+class FleetResult(TabuResult):
+    best_rot: np.ndarray = None   # rotary flags of best_open (ascending base ids)
+
+
+def fleet_tabu(C, K_r: int, K_f: int, heliport, rotary_only, R: int, T: int, N: int,
+               mode: int = 0, init_open=None, init_rot=None) -> FleetResult:
+    """Typed Tabu search; the best placement is returned in ascending base-id
+    order with the vehicle types permuted alongside."""
+    C, B, M = _cm(C)
+    K = int(K_r) + int(K_f)
+    init = None if init_open is None else np.ascontiguousarray(init_open, dtype=np.int32)
+    irot = None if init_rot is None else _flags(init_rot, K)
+    best = np.zeros(K, dtype=np.int32)
+    brot = np.zeros(K, dtype=np.int32)
+    cov = _c.c_int32()
+    dist = _c.c_int64()
+    it = _c.c_int32()
+    n = max(int(N), 0)
+    arr = [np.zeros(n, dtype=np.int32) for _ in range(4)]
+    cur_d = np.zeros(n, dtype=np.int64)
+    best_c = np.zeros(n, dtype=np.int32)
+    best_d = np.zeros(n, dtype=np.int64)
+    rc = _load().fso_fleet_tabu(C, M, B, M, int(K_r), int(K_f), _flags(heliport, B),
+                                _flags(rotary_only, M), int(R), int(T), int(N), int(mode),
+                                init, irot, best, brot, _c.byref(cov), _c.byref(dist),
+                                _c.byref(it), arr[0], arr[1], arr[2], arr[3], cur_d, best_c,
+                                best_d)
+    if rc != 0:
+        raise ValueError("oracle fleet tabu: invalid arguments or bases cannot hold the fleet")
+    order = np.argsort(best, kind="stable")
+    return FleetResult(best[order], int(cov.value), int(dist.value), int(it.value), arr[0],
+                       arr[1], arr[2], arr[3], cur_d, best_c, best_d, brot[order])
+
+
+def fleet_brute_optimum(C, K_r: int, K_f: int, heliport, rotary_only, R: int):
+    """(bases in slot order: rotary then fixed, types, cov, dist, placements)."""
+    C, B, M = _cm(C)
+    K = int(K_r) + int(K_f)
+    best = np.zeros(max(K, 1), dtype=np.int32)
+    brot = np.zeros(max(K, 1), dtype=np.int32)
+    cov = _c.c_int32()
+    dist = _c.c_int64()
+    n = _c.c_int64()
+    _load().fso_fleet_brute_optimum(C, M, B, M, int(K_r), int(K_f), _flags(heliport, B),
+                                    _flags(rotary_only, M), int(R), best, brot, _c.byref(cov),
+                                    _c.byref(dist), _c.byref(n))
+    return best[:K], brot[:K], int(cov.value), int(dist.value), int(n.value)

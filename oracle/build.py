@@ -7,14 +7,14 @@ import subprocess
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(_HERE, "fleetstage_oracle.c")
+SRCS = [os.path.join(_HERE, "fleetstage_oracle.c"), os.path.join(_HERE, "fleet_oracle.c")]
 OUT = os.path.join(_HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=c11", "-O3", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
-           "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+           "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
