@@ -163,6 +163,55 @@ fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int
                         int32_t *best_open_out, fs_score *score_out,
                         int32_t *assign_out, fs_trace_rec *trace_out, void *stream);
 
+/* ---------------------------------------------------------------- heterogeneous fleet
+ *
+ * The paper's full model (Section 3, Eq. 4-10): K_r rotary-wing and K_f
+ * fixed-wing vehicles; bases are aerodromes (either type) or heliports
+ * (rotary-wing only), at most one vehicle per base (Eq. 6, 7); a rotary-only
+ * mission (rho = 1, Eq. 10) can be flown by a rotary-wing vehicle only.  Each
+ * mission is flown from its nearest compatible occupied base; coverage within
+ * range and the (coverage, distance) order are those of the homogeneous calls.
+ * With no heliport, no rotary-only mission and K_f = 0 the calls below give
+ * exactly what fs_move_scores / fs_tabu_solve give. */
+typedef struct {
+    int32_t rotary;              /* K_r >= 0 rotary-wing vehicles */
+    int32_t fixed;               /* K_f >= 0 fixed-wing vehicles; K = K_r + K_f >= 1 */
+    const int32_t *heliport;     /* device, B: nonzero = heliport, 0 = aerodrome */
+    const int32_t *rotary_only;  /* device, M: nonzero = rotary-only mission, or NULL (none) */
+} fs_fleet;
+
+/* Score of every relocation of one vehicle (the typed checks of Section 4.3):
+ * for slot k (base open[k], rotary[k] != 0 for a rotary-wing vehicle) and base
+ * j, the value of the placement with that vehicle moved to j.  cov_out and
+ * dist_out (device, K x B, row k = slot k) hold -1 where j is occupied or is a
+ * heliport and the vehicle fixed-wing.  open and rotary are device arrays of K
+ * (K distinct ids, exactly fleet->rotary rotary-wing, none fixed-wing on a
+ * heliport).  FS_E_INVALID on any violation (nothing is written). */
+fs_status fs_fleet_move_scores(const int32_t *C, int64_t ldc, int32_t B, int32_t M,
+                               const fs_fleet *fleet, const int32_t *open,
+                               const int32_t *rotary, int32_t range_m, int32_t *cov_out,
+                               int64_t *dist_out, void *stream);
+
+/* Tabu search (mode 0) or local search (mode 1) over vehicle relocations,
+ * exactly as fs_tabu_solve otherwise (tabu list, aspiration, order (cov desc,
+ * dist asc, out-base asc, in-base asc), N iterations).  init_open / init_rotary
+ * (device, K) give the initial placement and its vehicle types, or init_open =
+ * NULL for the typed base ranking of Algorithm 1 (lines 13-21): bases in
+ * (row sum, id) order, a heliport taken only while fewer than K_r are,
+ * rotary-wing vehicles on the chosen heliports and then on the best-ranked
+ * chosen aerodromes, fixed-wing on the rest.  A vehicle keeps its type when it
+ * moves.  best_open_out (device, K): best placement in ascending ids;
+ * best_rotary_out (device, K): their vehicle types; assign_out (device, M, or
+ * NULL): nearest compatible base of each mission of the best placement (lowest
+ * id among equal costs) or -1; trace_out (device, N records, or NULL).
+ * FS_E_INVALID for a fleet the bases cannot hold (fewer than K_f aerodromes,
+ * or fewer than K usable bases) and the checks of fs_tabu_solve. */
+fs_status fs_fleet_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M,
+                         const fs_fleet *fleet, const fs_params *p, const int32_t *init_open,
+                         const int32_t *init_rotary, int32_t *best_open_out,
+                         int32_t *best_rotary_out, fs_score *score_out, int32_t *assign_out,
+                         fs_trace_rec *trace_out, void *stream);
+
 /* One instance of a batch (host struct; pointers are device pointers).
  *   C, ldc, B, M, K, range_m  as for fs_tabu_solve
  *   init_open      device K ids, or NULL (base ranking)

@@ -55,6 +55,14 @@ def run(fs, torch, n: int | None = None, reps: int = 2, log=print):
     batched()   # warm-up
     pl, t_plain = timed(plain)
     ba, t_batch = timed(batched)
+    # per-launch device time of the batched iteration's two kernels (every
+    # 16th launch stamped)
+    fs.timing_enable(True, every=16)
+    batched()
+    torch.cuda.synchronize()
+    sweep_ms, sweep_n = fs.timing_read("sweep")
+    refresh_ms, refresh_n = fs.timing_read("refresh")
+    fs.timing_enable(False)
     bad = 0
     for a, b in zip(pl, ba):
         same = (np.array_equal(a.best_open.cpu().numpy(), b.best_open.cpu().numpy())
@@ -67,5 +75,9 @@ def run(fs, torch, n: int | None = None, reps: int = 2, log=print):
                       "mm_evals_per_s": evals / t_plain},
             "batched": {"solves_per_s": n / t_batch, "s": t_batch,
                         "mm_evals_per_s": evals / t_batch,
-                        "sweep_bytes_per_iteration": bytes_per_iter},
+                        "sweep_bytes_per_iteration": bytes_per_iter,
+                        "sweep_us_per_launch": 1e3 * sweep_ms / max(sweep_n, 1),
+                        "refresh_us_per_launch": 1e3 * refresh_ms / max(refresh_n, 1),
+                        "sweep_gb_per_s": bytes_per_iter / max(sweep_ms / max(sweep_n, 1), 1e-9)
+                        / 1e6},
             "identical": bad == 0, "mismatched_instances": bad}

@@ -31,13 +31,15 @@ struct InstDesc {
     int32_t *open_tabu;      // K      slot -> last iteration its base is tabu
     int32_t *closed_tabu;    // B - K  (kept beside the lists so that no kernel
                              //        has to look a base's tabu state up by id)
-    int32_t *b1, *b2, *o1;   // Mp: nearest open cost, second-nearest, nearest slot
+    int32_t *b1, *b2, *o1;   // Mp: nearest cost, second-nearest, nearest slot (low 16
+                             // bits) and the mission kind (bit 16: rotary-only, whose
+                             // nearest and second-nearest are over rotary slots only)
     Acc *acc[2];             // kStripes x (K + 1): G at [s][0], L_k at [s][1 + k]
     Candidate *cand;         // max(ngroups, 1): best admissible move per row group
     SolveState *st;
     int32_t *best_open;      // K (slot order)
     int32_t *best_sorted;    // K ascending
-    int32_t *part_cov;       // nsplit x nclosed x (K + 1) when nsplit > 1
+    int32_t *part_cov;       // nsplit x nclosed x (K + 2) when nsplit > 1
     int64_t *part_dist;
     fs_trace_rec *trace;     // N records or NULL
     int32_t *sc_cov;         // optional full score table, K x B
@@ -47,6 +49,19 @@ struct InstDesc {
     int32_t pad1;
     int32_t *best_out;       // K ascending ids (caller's buffer), or NULL
     int32_t *assign_out;     // M mission -> base ids (caller's buffer), or NULL
+    // heterogeneous fleet (all zero / NULL for a homogeneous one: every vehicle
+    // rotary-wing, every base an aerodrome, no rotary-only mission)
+    int32_t typed;
+    int32_t K_r;             // rotary-wing vehicles (the first K_r of a ranked placement)
+    const int32_t *base_hel; // B: 1 = heliport (rotary-wing only), caller's buffer
+    const int32_t *rho;      // M: 1 = rotary-only mission, caller's buffer, or NULL
+    const int32_t *init_rot; // K: vehicle types of a given initial placement, or NULL
+    int32_t *open_rot;       // K   slot -> 1 if its vehicle is rotary-wing (fixed per slot)
+    int32_t *open_hel;       // K   slot -> 1 if its base is a heliport
+    int32_t *closed_hel;     // B-K slot -> 1 if its base is a heliport
+    int32_t *best_rot_sorted;// K   vehicle types of best_sorted
+    int32_t *rank_order;     // B   typed ranking: bases in (row sum, id) order
+    int32_t *best_rot_out;   // K   types of best_out (caller's buffer), or NULL
 };
 
 // One workgroup's share of the work.
@@ -74,7 +89,15 @@ struct EngineConfig {
     int J_tall = 4;     // rows per workgroup of the sweep_tall tiles
     int U_tall = 1;
     int Kmax_tall = 1;  // largest K among the sweep_tall instances
+    // missions per refresh workgroup: kRefreshMissions (the waves split the
+    // open slots of 64 missions) or kBlock (one mission per thread, all slots;
+    // for small K and many missions); the refresh tiles are built to match
+    int refresh_mpt = kRefreshMissions;
     int Kmax = 1;
+    // some instance has a typed fleet: the sweep keeps the rotary-only
+    // missions' common term apart (queued or scalar variant, U = 1, 256
+    // threads; other launch sets never pay for it)
+    bool typed = false;
 };
 
 // Device tables of a launch set.
@@ -109,7 +132,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
 // Host-side tile tables for a set of instance plans.
 void build_tiles(const std::vector<InstPlan> &plans, const std::vector<int32_t> &Mp,
                  std::vector<Tile> &sweep, std::vector<Tile> &score,
-                 std::vector<Tile> &refresh);
+                 std::vector<Tile> &refresh, int refresh_mpt = kRefreshMissions);
 
 // Launches (stream-ordered).  `step` is the launch step: iteration
 // step - start_step of every instance.
@@ -119,6 +142,9 @@ fs_status engine_reset(const EngineTables &t, int32_t maxB, int32_t Kmax, hipStr
 // ids) and closed list (the complement, ascending).
 fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nrow_tiles,
                             int32_t Bmax, hipStream_t s);
+// Heterogeneous fleets (typed instances only): heliport flags beside the open
+// and closed lists, and the vehicle types of a given initial placement.
+fs_status engine_fleet_lists(const EngineTables &t, hipStream_t s);
 // State of the initial placement, then cur = best = its value.  step0 is the
 // launch step at which the instances' iteration 0 ends (their start_step).
 fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s);

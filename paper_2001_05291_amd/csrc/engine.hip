@@ -156,8 +156,15 @@ __global__ __launch_bounds__(kBlock) void k_reset(const InstDesc *__restrict__ d
     const InstDesc &d = descs[inst];
     if (!d.active) return;
     const int32_t q = blk * kBlock + threadIdx.x;
-    if (q < d.K) d.open_tabu[q] = 0;
-    if (q < max(d.nclosed, 1)) d.closed_tabu[q] = 0;
+    if (q < d.K) {
+        d.open_tabu[q] = 0;
+        d.open_rot[q] = 1;   // homogeneous fleets: every vehicle rotary-wing on an
+        d.open_hel[q] = 0;   // aerodrome (the typed list kernels overwrite these)
+    }
+    if (q < max(d.nclosed, 1)) {
+        d.closed_tabu[q] = 0;
+        d.closed_hel[q] = 0;
+    }
     if (q < kStripes * (d.K + 1)) {
         d.acc[0][q].cov = 0;
         d.acc[0][q].dist = 0;
@@ -194,6 +201,101 @@ __global__ __launch_bounds__(kBlock) void k_rank_rows(const InstDesc *__restrict
 // < K form the open list of S_1, the others its closed list, both in
 // ascending id order (the lists the single-instance path builds on the host).
 // Sums are compared from LDS tiles; positions come from a prefix count.
+// Exclusive prefix of one count per thread (thread 0 runs the 256-entry scan);
+// returns this thread's offset and sets *total.  Every thread must call it.
+__device__ int32_t block_exclusive(int32_t v, int32_t *s_cnt, int32_t *total)
+{
+    __syncthreads();
+    s_cnt[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < kBlock; ++w) {
+            const int32_t c = s_cnt[w];
+            s_cnt[w] = run;
+            run += c;
+        }
+        s_cnt[kBlock] = run;
+    }
+    __syncthreads();
+    const int32_t r = s_cnt[threadIdx.x];
+    *total = s_cnt[kBlock];
+    return r;
+}
+
+// Typed base ranking (heterogeneous fleet, Algorithm 1 lines 13-21): walking
+// the bases in (row sum, id) order, a heliport is taken only while fewer than
+// K_r heliports are; the first K bases so taken are chosen.  Slots: the chosen
+// heliports first, then the chosen aerodromes, each in rank order; vehicles:
+// rotary-wing on the heliports and on the first K_r - (heliports chosen)
+// aerodromes, fixed-wing on the rest.  Each thread walks a contiguous run of
+// rank positions; the running counts come from block prefixes.  Sets sel[b].
+__device__ void rank_typed(const InstDesc &d, unsigned char *sel, int32_t *s_cnt)
+{
+    const int32_t B = d.B, K = d.K, Kr = d.K_r;
+    const int32_t *ord = d.rank_order;
+    const int32_t *hel = d.base_hel;
+    const int32_t per = (B + kBlock - 1) / kBlock;
+    const int32_t lo = min(B, (int32_t)threadIdx.x * per), hi = min(B, lo + per);
+    int32_t tot;
+    // heliports before each rank position
+    int32_t nh = 0;
+    for (int32_t r = lo; r < hi; ++r) nh += hel[ord[r]] != 0;
+    const int32_t h0 = block_exclusive(nh, s_cnt, &tot);
+    // eligible bases (aerodromes, and the first K_r heliports) before each position
+    int32_t ne = 0, h = h0;
+    for (int32_t r = lo; r < hi; ++r) {
+        const int32_t hb = hel[ord[r]] != 0;
+        ne += !hb || h < Kr;
+        h += hb;
+    }
+    const int32_t e0 = block_exclusive(ne, s_cnt, &tot);
+    // chosen heliports / aerodromes before each position
+    int32_t ch = 0, ca = 0;
+    h = h0;
+    int32_t e = e0;
+    for (int32_t r = lo; r < hi; ++r) {
+        const int32_t hb = hel[ord[r]] != 0;
+        const bool elig = !hb || h < Kr;
+        if (elig && e < K) {
+            ch += hb;
+            ca += !hb;
+        }
+        e += elig;
+        h += hb;
+    }
+    int32_t n_hel;
+    const int32_t ch0 = block_exclusive(ch, s_cnt, &n_hel);
+    const int32_t ca0 = block_exclusive(ca, s_cnt, &tot);
+    h = h0;
+    e = e0;
+    ch = ch0;
+    ca = ca0;
+    const int32_t rot_aero = Kr - n_hel;
+    for (int32_t r = lo; r < hi; ++r) {
+        const int32_t b = ord[r];
+        const int32_t hb = hel[b] != 0;
+        const bool elig = !hb || h < Kr;
+        if (elig && e < K) {
+            int32_t slot, rot;
+            if (hb) {
+                slot = ch++;
+                rot = 1;
+            } else {
+                slot = n_hel + ca;
+                rot = ca < rot_aero;
+                ++ca;
+            }
+            d.open[slot] = b;
+            d.open_rot[slot] = rot;
+            sel[b] = 1;
+        }
+        e += elig;
+        h += hb;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restrict__ descs)
 {
     const InstDesc &d = descs[blockIdx.x];
@@ -201,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restric
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *sel = smem;   // B flags
     __shared__ int64_t tile[kBlock];
-    __shared__ int32_t s_cnt[kBlock];
+    __shared__ int32_t s_cnt[kBlock + 1];
     const int32_t B = d.B, K = d.K;
     for (int32_t b0 = 0; b0 < B; b0 += kBlock) {
         const int32_t b = b0 + threadIdx.x;
@@ -217,9 +319,13 @@ __global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restric
                 rank += (o < mine) || (o == mine && t0 + q < b);
             }
         }
-        if (b < B) sel[b] = rank < K;
+        if (b < B) {
+            sel[b] = !d.typed && rank < K;
+            if (d.typed) d.rank_order[rank] = b;
+        }
     }
     __syncthreads();
+    if (d.typed) rank_typed(d, sel, s_cnt);
     const int32_t per = (B + kBlock - 1) / kBlock;
     const int32_t lo = min(B, (int32_t)threadIdx.x * per), hi = min(B, lo + per);
     int32_t cnt = 0;
@@ -239,12 +345,26 @@ __global__ __launch_bounds__(kBlock) void k_rank_lists(const InstDesc *__restric
     int32_t *op = d.open, *cl = d.closed;
     for (int32_t b = lo; b < hi; ++b) {
         if (sel[b]) {
-            op[before] = b;
+            if (!d.typed) op[before] = b;   // typed: slot order set by rank_typed
             ++before;
         } else {
             cl[b - before] = b;
         }
     }
+}
+
+// Heterogeneous fleets: heliport flags beside both lists, and the vehicle types
+// of a given initial placement.  grid = ninst; after the lists are in place.
+__global__ __launch_bounds__(kBlock) void k_fleet_lists(const InstDesc *__restrict__ descs)
+{
+    const InstDesc &d = descs[blockIdx.x];
+    if (!d.active || !d.typed) return;
+    for (int32_t k = threadIdx.x; k < d.K; k += kBlock) {
+        d.open_hel[k] = d.base_hel[d.open[k]] != 0;
+        if (d.init_rot) d.open_rot[k] = d.init_rot[k] != 0;
+    }
+    for (int32_t q = threadIdx.x; q < d.nclosed; q += kBlock)
+        d.closed_hel[q] = d.base_hel[d.closed[q]] != 0;
 }
 
 // ---------------------------------------------------------------- refresh (A2, A4, A5)
@@ -277,7 +397,9 @@ __device__ void write_record(const InstDesc &d, int32_t t, const SolveState &s, 
 // their loads together, and merge nearest / second-nearest in LDS; ties in the
 // nearest cost go to the lower base id.  G and L_k are summed in LDS, then
 // added with integer atomics into one of kStripes accumulator copies (exact in
-// any order).
+// any order).  TY: the launch set holds a typed fleet (vehicle types per slot,
+// rotary-only missions, base kinds travelling with the swapped bases).
+template <int MPT, bool TY>
 __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__ descs,
                                                     const Tile *__restrict__ tiles, int32_t step)
 {
@@ -294,6 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     u64 *s_cov = reinterpret_cast<u64 *>(smem);
     u64 *s_dist = s_cov + (K + 1);
     int32_t *s_open = reinterpret_cast<int32_t *>(s_dist + (K + 1));
+    int32_t *s_rot = s_open + K;   // vehicle type per slot (never changes in a search)
     __shared__ int32_t p_v1[kBlock / 64][64], p_i1[kBlock / 64][64], p_s1[kBlock / 64][64],
         p_v2[kBlock / 64][64];
     __shared__ Candidate s_red[kBlock / 64 + 1];
@@ -312,7 +435,10 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             if (cand_better(c, best)) best = c;
         }
         const int32_t *cur_open = d.open;
-        for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = cur_open[k];
+        for (int k = threadIdx.x; k < K; k += kBlock) {
+            s_open[k] = cur_open[k];
+            if (TY) s_rot[k] = d.open_rot[k];
+        }
         best = block_best(best, s_red);   // barriers: s_open complete too
         if (!best.valid && d.mode == 1) {
             // local optimum: stop; the placement and its state stay as they are
@@ -349,6 +475,11 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                 d.open_tabu[best.i_slot] = t + d.T;
                 d.closed[best.j_slot] = best.i_base;
                 d.closed_tabu[best.j_slot] = t + d.T;
+                if (TY && d.typed) {   // the base kinds trade list slots with the bases
+                    const int32_t h = d.open_hel[best.i_slot];
+                    d.open_hel[best.i_slot] = d.closed_hel[best.j_slot];
+                    d.closed_hel[best.j_slot] = h;
+                }
             }
             if (s_improved)
                 for (int k = threadIdx.x; k < K; k += kBlock)
@@ -358,7 +489,10 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         if (best.valid && threadIdx.x == 0) s_open[best.i_slot] = best.j_base;
     } else {
         const int32_t *first = d.open;
-        for (int k = threadIdx.x; k < K; k += kBlock) s_open[k] = first[k];
+        for (int k = threadIdx.x; k < K; k += kBlock) {
+            s_open[k] = first[k];
+            if (TY) s_rot[k] = d.open_rot[k];
+        }
     }
     for (int k = threadIdx.x; k <= K; k += kBlock) {
         s_cov[k] = 0;
@@ -367,62 +501,105 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int32_t m = tl.g * kRefreshMissions + lane;
-    int32_t v1 = INT32_MAX, i1 = INT32_MAX, s1 = 0, v2 = INT32_MAX;
-    if (m < M) {
-        const int32_t *col = d.C + m;
-        constexpr int W = kBlock / 64, UNR = 16;
-        for (int32_t k0 = wave; k0 < K; k0 += W * UNR) {
-            int32_t c[UNR], id[UNR];
+    int32_t m, v1 = INT32_MAX, i1 = INT32_MAX, s1 = 0, v2 = INT32_MAX;
+    bool owner;   // this thread holds mission m's final nearest / second-nearest
+    int32_t kind; // 1: a rotary-only mission (only rotary-wing slots can fly it)
+    if constexpr (MPT == kBlock) {
+        // one mission per thread, every open slot in turn (small K)
+        m = tl.g * MPT + threadIdx.x;
+        owner = true;
+        kind = (TY && d.rho && m < M) ? (d.rho[m] != 0) : 0;
+        if (m < M) {
+            const int32_t *col = d.C + m;
+            constexpr int UNR = 16;
+            for (int32_t k0 = 0; k0 < K; k0 += UNR) {
+                int32_t c[UNR], id[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int32_t k = k0 + W * u;
-                id[u] = k < K ? s_open[k] : 0;
-                c[u] = k < K ? col[(int64_t)id[u] * ldc] : INT32_MAX;
-            }
+                for (int u = 0; u < UNR; ++u) {
+                    const int32_t k = k0 + u;
+                    const bool ok = k < K && (!TY || !kind || s_rot[k]);
+                    id[u] = ok ? s_open[k] : 0;
+                    c[u] = ok ? col[(int64_t)id[u] * ldc] : INT32_MAX;
+                }
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int32_t k = k0 + W * u;
-                if (k < K) {
-                    if (c[u] < v1 || (c[u] == v1 && id[u] < i1)) {
-                        v2 = v1;
-                        v1 = c[u];
-                        i1 = id[u];
-                        s1 = k;
-                    } else if (c[u] < v2) {
-                        v2 = c[u];
+                for (int u = 0; u < UNR; ++u) {
+                    const int32_t k = k0 + u;
+                    if (k < K && (!TY || !kind || s_rot[k])) {
+                        if (c[u] < v1 || (c[u] == v1 && id[u] < i1)) {
+                            v2 = v1;
+                            v1 = c[u];
+                            i1 = id[u];
+                            s1 = k;
+                        } else if (c[u] < v2) {
+                            v2 = c[u];
+                        }
                     }
                 }
             }
         }
-    }
-    p_v1[wave][lane] = v1;
-    p_i1[wave][lane] = i1;
-    p_s1[wave][lane] = s1;
-    p_v2[wave][lane] = v2;
-    __syncthreads();
-    if (wave == 0) {
-        v1 = p_v1[0][lane];
-        i1 = p_i1[0][lane];
-        s1 = p_s1[0][lane];
-        v2 = p_v2[0][lane];
+    } else {
+        m = tl.g * MPT + lane;
+        owner = wave == 0;
+        kind = (TY && d.rho && m < M) ? (d.rho[m] != 0) : 0;
+        if (m < M) {
+            const int32_t *col = d.C + m;
+            constexpr int W = kBlock / 64, UNR = 16;
+            for (int32_t k0 = wave; k0 < K; k0 += W * UNR) {
+                int32_t c[UNR], id[UNR];
 #pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) {
-            const int32_t bv1 = p_v1[w][lane], bi1 = p_i1[w][lane];
-            if (bv1 < v1 || (bv1 == v1 && bi1 < i1)) {
-                v2 = min(v1, p_v2[w][lane]);
-                v1 = bv1;
-                i1 = bi1;
-                s1 = p_s1[w][lane];
-            } else {
-                v2 = min(v2, bv1);
+                for (int u = 0; u < UNR; ++u) {
+                    const int32_t k = k0 + W * u;
+                    const bool ok = k < K && (!TY || !kind || s_rot[k]);
+                    id[u] = ok ? s_open[k] : 0;
+                    c[u] = ok ? col[(int64_t)id[u] * ldc] : INT32_MAX;
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int32_t k = k0 + W * u;
+                    if (k < K && (!TY || !kind || s_rot[k])) {
+                        if (c[u] < v1 || (c[u] == v1 && id[u] < i1)) {
+                            v2 = v1;
+                            v1 = c[u];
+                            i1 = id[u];
+                            s1 = k;
+                        } else if (c[u] < v2) {
+                            v2 = c[u];
+                        }
+                    }
+                }
             }
         }
+        // the waves split the open slots of the same 64 missions: merge in LDS
+        p_v1[wave][lane] = v1;
+        p_i1[wave][lane] = i1;
+        p_s1[wave][lane] = s1;
+        p_v2[wave][lane] = v2;
+        __syncthreads();
+        if (wave == 0) {
+            v1 = p_v1[0][lane];
+            i1 = p_i1[0][lane];
+            s1 = p_s1[0][lane];
+            v2 = p_v2[0][lane];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) {
+                const int32_t bv1 = p_v1[w][lane], bi1 = p_i1[w][lane];
+                if (bv1 < v1 || (bv1 == v1 && bi1 < i1)) {
+                    v2 = min(v1, p_v2[w][lane]);
+                    v1 = bv1;
+                    i1 = bi1;
+                    s1 = p_s1[w][lane];
+                } else {
+                    v2 = min(v2, bv1);
+                }
+            }
+        }
+    }
+    if (owner) {
         int32_t g1c = 0, g1d = 0;
         if (m < M) {
             d.b1[m] = v1;
             d.b2[m] = v2;
-            d.o1[m] = s1;
+            d.o1[m] = s1 | (kind << 16);
             g1c = v1 <= R;
             g1d = g1c ? v1 : 0;
             const int32_t g2c = v2 <= R;
@@ -477,23 +654,38 @@ __global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restric
 
 // ---------------------------------------------------------------- sweep (A3, A4 local)
 
+// t1c[0 .. NC-1], t1d[0 .. NC-1]: the row's common term; with NC = 2 split
+// over ordinary [0] and rotary-only [1] missions (o1 bit 16; a homogeneous
+// fleet has none, NC = 1).  The bin is the low 16 bits of o1.
+template <int NC>
 __device__ __forceinline__ void visit(int32_t c, int32_t b1, int32_t b2, int32_t o1, int32_t g1c,
                                       int32_t g1d, int32_t g2c, int32_t g2d, int32_t R,
-                                      int32_t &t1c, int64_t &t1d, int32_t *__restrict__ bc,
+                                      int32_t *t1c, int64_t *t1d, int32_t *__restrict__ bc,
                                       u64 *__restrict__ bd)
 {
     if (c < b2) {
         const int32_t v1 = min(c, b1);
         const int32_t u = max(c, b1);
         const int32_t cv = v1 <= R;
-        t1c += cv - g1c;
-        t1d += (int64_t)((cv ? v1 : 0) - g1d);
+        const int32_t tc = cv - g1c;
+        const int32_t td = (cv ? v1 : 0) - g1d;
+        if constexpr (NC == 1) {
+            t1c[0] += tc;
+            t1d[0] += (int64_t)td;
+        } else {
+            const bool rot_only = (o1 >> 16) != 0;
+            t1c[0] += rot_only ? 0 : tc;
+            t1c[1] += rot_only ? tc : 0;
+            t1d[0] += (int64_t)(rot_only ? 0 : td);
+            t1d[1] += (int64_t)(rot_only ? td : 0);
+        }
         const int32_t cu = u <= R;
         const int32_t dc = cu - g2c;
         const int32_t dd = (cu ? u : 0) - g2d;
+        const int32_t slot = o1 & 0xFFFF;
         if (dc | dd) {
-            atomicAdd(bc + o1, dc);
-            atomicAdd(bd + o1, (u64)(int64_t)dd);
+            atomicAdd(bc + slot, dc);
+            atomicAdd(bd + slot, (u64)(int64_t)dd);
         }
     }
 }
@@ -501,7 +693,7 @@ __device__ __forceinline__ void visit(int32_t c, int32_t b1, int32_t b2, int32_t
 // LDS of the sweep / score kernels for J rows and up to Kmax slots.
 __host__ __device__ constexpr size_t sweep_lds_bytes(int J, int Kmax)
 {
-    return (size_t)J * Kmax * 12 + (size_t)(Kmax + 1) * 12 + (size_t)Kmax * 8 + 16;
+    return (size_t)J * Kmax * 12 + (size_t)(Kmax + 1) * 12 + (size_t)Kmax * 12 + 16;
 }
 
 struct SweepLds {
@@ -511,6 +703,7 @@ struct SweepLds {
     int32_t *Lc;    // K+1: G, L_k coverage
     int32_t *open;  // K: open base of each slot
     int32_t *otabu; // K: tabu expiry of each open slot
+    int32_t *orot;  // K: 1 if the slot's vehicle is rotary-wing
 };
 
 __device__ __forceinline__ SweepLds carve_lds(unsigned char *smem, int J, int K)
@@ -522,13 +715,16 @@ __device__ __forceinline__ SweepLds carve_lds(unsigned char *smem, int J, int K)
     s.Lc = s.bc + J * K;
     s.open = s.Lc + (K + 1);
     s.otabu = s.open + K;
+    s.orot = s.otabu + K;
     return s;
 }
 
 // Per-slot inputs of the scoring step, loaded before the streaming loop so
 // their latency overlaps it: G and L_k (summed over the stripes), the open
-// list and the tabu state of the open bases.
-__device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, const SweepLds &L)
+// list, the tabu state of the open bases and (typed fleets) their vehicle
+// types; without types every slot counts as rotary-wing on an aerodrome.
+__device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, const SweepLds &L,
+                                                 bool typed)
 {
     const int32_t K = d.K;
     const Acc *acc = d.acc[t & 1];
@@ -543,6 +739,7 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
         if (k < K) {
             L.open[k] = op[k];
             L.otabu[k] = ot[k];
+            L.orot[k] = typed ? d.open_rot[k] : 1;
         }
     }
 }
@@ -554,9 +751,11 @@ __device__ __forceinline__ void load_slot_inputs(const InstDesc &d, int32_t t, c
 // kernel start).  When the group has at most 64 moves the first wave scores
 // them alone and the rest of the workgroup may leave.
 template <int BS>
-__device__ void score_group(const InstDesc &d, const SolveState &st, int J, int32_t t, int32_t g,
-                            const int32_t *s_jrow, const int32_t *s_jtabu, const SweepLds &L,
-                            const int32_t *t1c, const int64_t *t1d, Candidate *s_red)
+__device__ void score_group(const InstDesc &d, const SolveState &st, int J, int NC, int32_t t,
+                            int32_t g,
+                            const int32_t *s_jrow, const int32_t *s_jtabu, const int32_t *s_jhel,
+                            const SweepLds &L, const int32_t *t1c, const int64_t *t1d,
+                            Candidate *s_red)
 {
     const int32_t K = d.K;
     const bool one_wave = J * K <= 64;
@@ -570,8 +769,14 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int3
         const int32_t r = idx / K, k = idx - r * K;
         const int32_t js = g * J + r;
         if (js >= d.nclosed) continue;
-        const int32_t cov = Gc + L.Lc[1 + k] + t1c[r] + L.bc[idx];
-        const int64_t dist = Gd + L.Ld[1 + k] + t1d[r] + (int64_t)L.bd[idx];
+        // moving a fixed-wing vehicle changes nothing for rotary-only missions,
+        // and cannot land on a heliport
+        const bool rot = L.orot[k] != 0;
+        if (!rot && s_jhel[r]) continue;
+        const bool two = NC == 2 && rot;
+        const int32_t cov = Gc + L.Lc[1 + k] + t1c[NC * r] + (two ? t1c[NC * r + 1] : 0) + L.bc[idx];
+        const int64_t dist =
+            Gd + L.Ld[1 + k] + t1d[NC * r] + (two ? t1d[NC * r + 1] : 0) + (int64_t)L.bd[idx];
         const int32_t i = L.open[k], j = s_jrow[r];
         if (d.sc_cov) {
             d.sc_cov[(int64_t)k * d.B + j] = cov;
@@ -606,7 +811,7 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int3
     if (threadIdx.x == 0) d.cand[g] = mine;
 }
 
-template <int BS, int J, int U, bool NT>
+template <int BS, int J, int U, bool NT, int NC>
 __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jrow, int32_t m0,
                                            int32_t m1, int32_t *t1c, int64_t *t1d, int32_t *bc,
                                            u64 *bd)
@@ -648,8 +853,8 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
                 const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
 #pragma unroll
                 for (int r = 0; r < J; ++r)
-                    visit(cv[u][r][e], b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c[r], t1d[r], bc + r * K,
-                          bd + r * K);
+                    visit<NC>(cv[u][r][e], b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c + NC * r,
+                              t1d + NC * r, bc + r * K, bd + r * K);
             }
         }
     }
@@ -671,17 +876,18 @@ struct QueueRow {
     int32_t c[kQueue], b1[kQueue], b2[kQueue], o1[kQueue];
 };
 
+template <int NC>
 __device__ __forceinline__ void visit_queued(const QueueRow &qr, int32_t at, int32_t R,
-                                             int32_t &t1c, int64_t &t1d, int32_t *__restrict__ bc,
+                                             int32_t *t1c, int64_t *t1d, int32_t *__restrict__ bc,
                                              u64 *__restrict__ bd)
 {
     const int32_t c = qr.c[at], b1 = qr.b1[at], b2 = qr.b2[at], o1 = qr.o1[at];
     const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
     const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
-    visit(c, b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
+    visit<NC>(c, b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
 }
 
-template <int BS, int J, int U, bool NT>
+template <int BS, int J, int U, bool NT, int NC>
 __device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32_t *jrow,
                                                   int32_t m0, int32_t m1, int32_t *t1c,
                                                   int64_t *t1d, int32_t *bc, u64 *bd)
@@ -743,7 +949,8 @@ __device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32
                     if (len[r] >= 64) {
                         // score the oldest 64, then move the rest (at most 63) down
                         __builtin_amdgcn_wave_barrier();
-                        visit_queued(qr, lane, R, t1c[r], t1d[r], bc + r * K, bd + r * K);
+                        visit_queued<NC>(qr, lane, R, t1c + NC * r, t1d + NC * r, bc + r * K,
+                                         bd + r * K);
                         len[r] -= 64;
                         int32_t c = 0, b1 = 0, b2 = 0, o1 = 0;
                         if (lane < len[r]) {
@@ -768,10 +975,12 @@ __device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int r = 0; r < J; ++r)
-        if (lane < len[r]) visit_queued(s_q[wave][r], lane, R, t1c[r], t1d[r], bc + r * K, bd + r * K);
+        if (lane < len[r])
+            visit_queued<NC>(s_q[wave][r], lane, R, t1c + NC * r, t1d + NC * r, bc + r * K,
+                             bd + r * K);
 }
 
-template <int BS, int J>
+template <int BS, int J, int NC>
 __device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *jrow, int32_t m0,
                                              int32_t m1, int32_t *t1c, int64_t *t1d, int32_t *bc,
                                              u64 *bd)
@@ -788,7 +997,8 @@ __device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *j
         const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
 #pragma unroll
         for (int r = 0; r < J; ++r)
-            visit(cv[r], b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c[r], t1d[r], bc + r * K, bd + r * K);
+            visit<NC>(cv[r], b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c + NC * r, t1d + NC * r,
+                      bc + r * K, bd + r * K);
     }
 }
 
@@ -847,8 +1057,9 @@ __device__ void sweep_housekeeping(const InstDesc &d, int32_t t)
 // One workgroup = J closed rows x one mission chunk of one instance.  Tiles
 // are ordered chunk-minor so that consecutive block ids (which the dispatcher
 // spreads over the XCDs) split an instance's mission axis and each XCD's L2
-// holds the b1/b2/o1 of fewer chunks.
-template <int BS, int J, int U, bool VEC4, bool NT, bool Q>
+// holds the b1/b2/o1 of fewer chunks.  NC: common-term classes per row (2
+// when some instance of the launch set has a typed fleet, else 1).
+template <int BS, int J, int U, bool VEC4, bool NT, bool Q, int NC>
 __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs,
                                                   const Tile *__restrict__ tiles, int32_t step)
 {
@@ -863,11 +1074,13 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K;
     const SweepLds L = carve_lds(smem, J, K);
-    __shared__ int32_t s_jrow[J], s_jtabu[J];
-    __shared__ int32_t s_t1c[BS / 64][J];
-    __shared__ int64_t s_t1d[BS / 64][J];
-    __shared__ int32_t s_sum_c[J];
-    __shared__ int64_t s_sum_d[J];
+    __shared__ int32_t s_jrow[J], s_jtabu[J], s_jhel[J];
+    // per row: the common term (typed: over ordinary [2r] and rotary-only
+    // [2r + 1] missions)
+    __shared__ int32_t s_t1c[BS / 64][NC * J];
+    __shared__ int64_t s_t1d[BS / 64][NC * J];
+    __shared__ int32_t s_sum_c[NC * J];
+    __shared__ int64_t s_sum_d[NC * J];
     __shared__ Candidate s_red[BS / 64 + 1];
 
     if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
@@ -880,18 +1093,21 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
         const int32_t js = tl.g * J + threadIdx.x;
         const int32_t jc = js < nclosed ? js : 0;
         s_jrow[threadIdx.x] = nclosed > 0 ? d.closed[jc] : 0;
-        if (scoring) s_jtabu[threadIdx.x] = nclosed > 0 ? d.closed_tabu[jc] : 0;
+        if (scoring) {
+            s_jtabu[threadIdx.x] = nclosed > 0 ? d.closed_tabu[jc] : 0;
+            s_jhel[threadIdx.x] = NC == 2 && nclosed > 0 ? d.closed_hel[jc] : 0;
+        }
     }
-    if (scoring) load_slot_inputs(d, t, L);
+    if (scoring) load_slot_inputs(d, t, L, NC == 2);
     __syncthreads();
 
     int32_t jrow[J];
 #pragma unroll
     for (int r = 0; r < J; ++r) jrow[r] = s_jrow[r];
-    int32_t t1c[J];
-    int64_t t1d[J];
+    int32_t t1c[NC * J];
+    int64_t t1d[NC * J];
 #pragma unroll
-    for (int r = 0; r < J; ++r) {
+    for (int r = 0; r < NC * J; ++r) {
         t1c[r] = 0;
         t1d[r] = 0;
     }
@@ -899,30 +1115,32 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
         const int32_t m0 = tl.sp * d.chunk;
         const int32_t m1 = min(d.Mp, m0 + d.chunk);
         if (VEC4 && Q)
-            sweep_vec4_queued<BS, J, U, NT>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+            sweep_vec4_queued<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
         else if (VEC4)
-            sweep_vec4<BS, J, U, NT>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+            sweep_vec4<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
         else
-            sweep_scalar<BS, J>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+            sweep_scalar<BS, J, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
     }
-    reduce_rows<BS, J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
+    reduce_rows<BS, NC * J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
 
     if (scoring) {
-        score_group<BS>(d, st, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
+        score_group<BS>(d, st, J, NC, t, tl.g, s_jrow, s_jtabu, s_jhel, L, s_sum_c, s_sum_d,
+                        s_red);
     } else {
-        // partial sums of this chunk: [T1, bin_0 .. bin_{K-1}] per row
-        const int32_t K1 = K + 1;
-        for (int32_t idx = threadIdx.x; idx < J * K1; idx += BS) {
-            const int32_t r = idx / K1, k = idx - r * K1;
+        // partial sums of this chunk: [T1 ordinary, T1 rotary-only, bin_0 ..
+        // bin_{K-1}] per row
+        const int32_t K2 = K + 2;
+        for (int32_t idx = threadIdx.x; idx < J * K2; idx += BS) {
+            const int32_t r = idx / K2, k = idx - r * K2;
             const int32_t js = tl.g * J + r;
             if (js >= nclosed) continue;
-            const int64_t at = ((int64_t)tl.sp * nclosed + js) * K1 + k;
-            if (k == 0) {
-                d.part_cov[at] = s_sum_c[r];
-                d.part_dist[at] = s_sum_d[r];
+            const int64_t at = ((int64_t)tl.sp * nclosed + js) * K2 + k;
+            if (k < 2) {
+                d.part_cov[at] = k < NC ? s_sum_c[NC * r + k] : 0;
+                d.part_dist[at] = k < NC ? s_sum_d[NC * r + k] : 0;
             } else {
-                d.part_cov[at] = L.bc[r * K + k - 1];
-                d.part_dist[at] = (int64_t)L.bd[r * K + k - 1];
+                d.part_cov[at] = L.bc[r * K + k - 2];
+                d.part_dist[at] = (int64_t)L.bd[r * K + k - 2];
             }
         }
     }
@@ -941,11 +1159,11 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
     const SolveState st = *d.st;
     if (st.stopped) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int32_t K = d.K, K1 = K + 1;
+    const int32_t K = d.K, K2 = K + 2;
     const SweepLds L = carve_lds(smem, J, K);
-    __shared__ int32_t s_jrow[J], s_jtabu[J];
-    __shared__ int32_t s_sum_c[J];
-    __shared__ int64_t s_sum_d[J];
+    __shared__ int32_t s_jrow[J], s_jtabu[J], s_jhel[J];
+    __shared__ int32_t s_sum_c[2 * J];
+    __shared__ int64_t s_sum_d[2 * J];
     __shared__ Candidate s_red[kBlock / 64 + 1];
     const int32_t nclosed = d.nclosed;
     if (threadIdx.x < J) {
@@ -953,30 +1171,31 @@ __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ d
         const int32_t jc = js < nclosed ? js : 0;
         s_jrow[threadIdx.x] = d.closed[jc];
         s_jtabu[threadIdx.x] = d.closed_tabu[jc];
+        s_jhel[threadIdx.x] = d.typed ? d.closed_hel[jc] : 0;
     }
-    load_slot_inputs(d, t, L);
-    for (int32_t idx = threadIdx.x; idx < J * K1; idx += kBlock) {
-        const int32_t r = idx / K1, k = idx - r * K1;
+    load_slot_inputs(d, t, L, d.typed != 0);
+    for (int32_t idx = threadIdx.x; idx < J * K2; idx += kBlock) {
+        const int32_t r = idx / K2, k = idx - r * K2;
         const int32_t js = tl.g * J + r;
         int32_t c = 0;
         int64_t dd = 0;
         if (js < nclosed) {
             for (int32_t sp = 0; sp < d.nsplit; ++sp) {
-                const int64_t at = ((int64_t)sp * nclosed + js) * K1 + k;
+                const int64_t at = ((int64_t)sp * nclosed + js) * K2 + k;
                 c += d.part_cov[at];
                 dd += d.part_dist[at];
             }
         }
-        if (k == 0) {
-            s_sum_c[r] = c;
-            s_sum_d[r] = dd;
+        if (k < 2) {
+            s_sum_c[2 * r + k] = c;
+            s_sum_d[2 * r + k] = dd;
         } else {
-            L.bc[r * K + k - 1] = c;
-            L.bd[r * K + k - 1] = (u64)dd;
+            L.bc[r * K + k - 2] = c;
+            L.bd[r * K + k - 2] = (u64)dd;
         }
     }
     __syncthreads();
-    score_group<kBlock>(d, st, J, t, tl.g, s_jrow, s_jtabu, L, s_sum_c, s_sum_d, s_red);
+    score_group<kBlock>(d, st, J, 2, t, tl.g, s_jrow, s_jtabu, s_jhel, L, s_sum_c, s_sum_d, s_red);
 }
 
 // ---------------------------------------------------------------- outputs
@@ -995,7 +1214,9 @@ __global__ __launch_bounds__(kBlock) void k_outputs(const InstDesc *__restrict__
         int32_t pos = 0;
         for (int32_t q = 0; q < K; ++q) pos += d.best_open[q] < v;
         d.best_sorted[pos] = v;
+        d.best_rot_sorted[pos] = d.open_rot[k];   // a slot keeps its vehicle
         if (d.best_out) d.best_out[pos] = v;
+        if (d.best_rot_out) d.best_rot_out[pos] = d.open_rot[k];
     }
     if (threadIdx.x == 0) {
         const SolveState *st = d.st;
@@ -1020,17 +1241,20 @@ __global__ __launch_bounds__(kBlock) void k_outputs(const InstDesc *__restrict__
 // the first strict minimum is the lowest id among equal costs), or -1 beyond
 // R.  Tiles of 64 missions (the refresh tiles); one mission per thread of the
 // first wave.
+template <int MPT>
 __global__ __launch_bounds__(kBlock) void k_assign(const InstDesc *__restrict__ descs,
                                                    const Tile *__restrict__ tiles)
 {
     const Tile tl = tiles[blockIdx.x];
     const InstDesc &d = descs[tl.inst];
     if (!d.active || !d.assign_out) return;
-    if (threadIdx.x >= kRefreshMissions) return;
-    const int32_t m = tl.g * kRefreshMissions + threadIdx.x;
+    if (threadIdx.x >= MPT) return;
+    const int32_t m = tl.g * MPT + threadIdx.x;
     if (m >= d.M) return;
     int32_t v = INT32_MAX, who = -1;
+    const bool rot_only = d.rho && d.rho[m] != 0;
     for (int32_t k = 0; k < d.K; ++k) {
+        if (rot_only && !d.best_rot_sorted[k]) continue;
         const int32_t id = d.best_sorted[k];
         const int32_t c = d.C[(int64_t)id * d.ldc + m];
         if (c < v) {
@@ -1056,10 +1280,13 @@ void launch_timed(void (*kernel)(Params...), dim3 grid, dim3 block, uint32_t lds
 }
 
 
-template <int J, int U, bool VEC4, bool NT, bool Q>
+template <int J, int U, bool VEC4, bool NT, bool Q, int NC>
 fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
                          TimedLaunch &tm)
 {
+    if (c.typed != (NC == 2))
+        return fail(FS_E_INTERNAL, "sweep kernel with %d common-term classes for a %s launch set",
+                    NC, c.typed ? "typed" : "homogeneous");
     const uint32_t lds = (uint32_t)sweep_lds_bytes(J, c.Kmax);
     const bool score = t.nscore > 0;
     if (t.nsweep > 0) {
@@ -1067,16 +1294,16 @@ fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t s
         // 1024-thread workgroups: up to 2 rows with any variant; more rows
         // only with in-place scoring and one load in flight (LDS queues and
         // registers grow with the rows)
-        if constexpr (J <= 2 || (!Q && U == 1)) {
+        if constexpr (NC == 1 && (J <= 2 || (!Q && U == 1))) {
             if (c.wide) {
-                launch_timed(k_sweep<kWideBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep),
+                launch_timed(k_sweep<kWideBlock, J, U, VEC4, NT, Q, NC>, dim3(t.nsweep),
                              dim3(kWideBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
                              t.desc, t.sweep, step);
                 launched = true;
             }
         }
         if (!launched)
-            launch_timed(k_sweep<kBlock, J, U, VEC4, NT, Q>, dim3(t.nsweep), dim3(kBlock), lds,
+            launch_timed(k_sweep<kBlock, J, U, VEC4, NT, Q, NC>, dim3(t.nsweep), dim3(kBlock), lds,
                          s, tm.start(), score ? nullptr : tm.stop(), t.desc, t.sweep, step);
         FS_HIP(hipGetLastError());
         if (!score) tm.used();
@@ -1094,18 +1321,30 @@ template <int J, int U>
 fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
                           TimedLaunch &tm)
 {
-    if (!c.vec4) return launch_sweep_t<J, 1, false, false, false>(t, c, step, s, tm);
+    if (!c.vec4) return launch_sweep_t<J, 1, false, false, false, 1>(t, c, step, s, tm);
     if (c.queue)
-        return c.nt ? launch_sweep_t<J, U, true, true, true>(t, c, step, s, tm)
-                    : launch_sweep_t<J, U, true, false, true>(t, c, step, s, tm);
-    return c.nt ? launch_sweep_t<J, U, true, true, false>(t, c, step, s, tm)
-                : launch_sweep_t<J, U, true, false, false>(t, c, step, s, tm);
+        return c.nt ? launch_sweep_t<J, U, true, true, true, 1>(t, c, step, s, tm)
+                    : launch_sweep_t<J, U, true, false, true, 1>(t, c, step, s, tm);
+    return c.nt ? launch_sweep_t<J, U, true, true, false, 1>(t, c, step, s, tm)
+                : launch_sweep_t<J, U, true, false, false, 1>(t, c, step, s, tm);
+}
+
+// Typed launch sets: the queued variant (one load in flight, 256-thread
+// workgroups) or the scalar one.
+template <int J>
+fs_status launch_sweep_typed(const EngineTables &t, const EngineConfig &c, int32_t step,
+                             hipStream_t s, TimedLaunch &tm)
+{
+    if (!c.vec4) return launch_sweep_t<J, 1, false, false, false, 2>(t, c, step, s, tm);
+    return c.nt ? launch_sweep_t<J, 1, true, true, true, 2>(t, c, step, s, tm)
+                : launch_sweep_t<J, 1, true, false, true, 2>(t, c, step, s, tm);
 }
 
 template <int J>
 fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s,
                          TimedLaunch &tm)
 {
+    if (c.typed) return launch_sweep_typed<J>(t, c, step, s, tm);
     switch (c.U) {
     case 1: return launch_sweep_ju<J, 1>(t, c, step, s, tm);
     case 2: return launch_sweep_ju<J, 2>(t, c, step, s, tm);
@@ -1116,7 +1355,7 @@ fs_status launch_sweep_j(const EngineTables &t, const EngineConfig &c, int32_t s
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-size_t refresh_lds_bytes(int Kmax) { return 16 * (size_t)(Kmax + 1) + 4 * (size_t)Kmax + 16; }
+size_t refresh_lds_bytes(int Kmax) { return 16 * (size_t)(Kmax + 1) + 8 * (size_t)Kmax + 16; }
 
 }  // namespace
 
@@ -1178,13 +1417,17 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
     n += align_up(4 * nclosed, 256);                            // closed list
     n += align_up(4 * (size_t)K, 256);                          // open tabu expiries
     n += align_up(4 * nclosed, 256);                            // closed tabu expiries
+    n += 3 * align_up(4 * (size_t)K, 256);                      // open types, heliport flags,
+                                                                // best types
+    n += align_up(4 * nclosed, 256);                            // closed heliport flags
+    n += align_up(4 * (size_t)B, 256);                          // typed ranking order
     n += 3 * align_up(4 * Mp, 256);                             // b1 b2 o1
     n += 2 * align_up(sizeof(Acc) * kStripes * (K + 1), 256);   // accumulators
     n += align_up(sizeof(Candidate) * std::max(p.ngroups, 1), 256);
     n += align_up(sizeof(SolveState), 256);
     n += 2 * align_up(4 * (size_t)K, 256);                      // best_open, best_sorted
     if (p.nsplit > 1) {
-        const size_t np = (size_t)p.nsplit * p.nclosed * (K + 1);
+        const size_t np = (size_t)p.nsplit * p.nclosed * (K + 2);
         n += align_up(4 * np, 256) + align_up(8 * np, 256);
     }
     return n;
@@ -1204,6 +1447,11 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.closed = (int32_t *)take(4 * nclosed);
     d.open_tabu = (int32_t *)take(4 * (size_t)K);
     d.closed_tabu = (int32_t *)take(4 * nclosed);
+    d.open_rot = (int32_t *)take(4 * (size_t)K);
+    d.open_hel = (int32_t *)take(4 * (size_t)K);
+    d.best_rot_sorted = (int32_t *)take(4 * (size_t)K);
+    d.closed_hel = (int32_t *)take(4 * nclosed);
+    d.rank_order = (int32_t *)take(4 * (size_t)B);
     d.b1 = (int32_t *)take(4 * Mp);
     d.b2 = (int32_t *)take(4 * Mp);
     d.o1 = (int32_t *)take(4 * Mp);
@@ -1216,7 +1464,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.part_cov = nullptr;
     d.part_dist = nullptr;
     if (p.nsplit > 1) {
-        const size_t np = (size_t)p.nsplit * p.nclosed * (K + 1);
+        const size_t np = (size_t)p.nsplit * p.nclosed * (K + 2);
         d.part_cov = (int32_t *)take(4 * np);
         d.part_dist = (int64_t *)take(8 * np);
     }
@@ -1231,7 +1479,8 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
 }
 
 void build_tiles(const std::vector<InstPlan> &plans, const std::vector<int32_t> &Mp,
-                 std::vector<Tile> &sweep, std::vector<Tile> &score, std::vector<Tile> &refresh)
+                 std::vector<Tile> &sweep, std::vector<Tile> &score, std::vector<Tile> &refresh,
+                 int refresh_mpt)
 {
     sweep.clear();
     score.clear();
@@ -1243,7 +1492,7 @@ void build_tiles(const std::vector<InstPlan> &plans, const std::vector<int32_t> 
             for (int32_t sp = 0; sp < p.nsplit; ++sp) sweep.push_back(Tile{(int32_t)i, g, sp, 0});
         if (p.nsplit > 1)
             for (int32_t g = 0; g < p.ngroups; ++g) score.push_back(Tile{(int32_t)i, g, 0, 0});
-        const int32_t nt = (Mp[i] + kRefreshMissions - 1) / kRefreshMissions;
+        const int32_t nt = (Mp[i] + refresh_mpt - 1) / refresh_mpt;
         for (int32_t g = 0; g < nt; ++g) refresh.push_back(Tile{(int32_t)i, g, 0, 0});
     }
 }
@@ -1271,10 +1520,29 @@ fs_status engine_rank_lists(const EngineTables &t, const Tile *row_tiles, int nr
     return FS_OK;
 }
 
+fs_status engine_fleet_lists(const EngineTables &t, hipStream_t s)
+{
+    k_fleet_lists<<<t.ninst, kBlock, 0, s>>>(t.desc);
+    FS_HIP(hipGetLastError());
+    return FS_OK;
+}
+
+namespace {
+typedef void (*RefreshKernel)(const InstDesc *, const Tile *, int32_t);
+
+RefreshKernel refresh_kernel(const EngineConfig &c)
+{
+    if (c.refresh_mpt == kBlock)
+        return c.typed ? k_refresh<kBlock, true> : k_refresh<kBlock, false>;
+    return c.typed ? k_refresh<kRefreshMissions, true> : k_refresh<kRefreshMissions, false>;
+}
+}  // namespace
+
 fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s)
 {
     if (t.nrefresh > 0) {
-        k_refresh<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh, step0);
+        refresh_kernel(c)<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh,
+                                                                               step0);
         FS_HIP(hipGetLastError());
     }
     k_init_score<<<t.ninst, kBlock, 0, s>>>(t.desc);
@@ -1290,7 +1558,9 @@ fs_status sweep_rows(const EngineTables &t, const EngineConfig &c, int32_t step,
     case 1: return launch_sweep_j<1>(t, c, step, s, timed);
     case 2: return launch_sweep_j<2>(t, c, step, s, timed);
     case 4: return launch_sweep_j<4>(t, c, step, s, timed);
-    case 8: return launch_sweep_ju<8, 1>(t, c, step, s, timed);
+    case 8:
+        return c.typed ? launch_sweep_typed<8>(t, c, step, s, timed)
+                       : launch_sweep_ju<8, 1>(t, c, step, s, timed);
     default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
     }
 }
@@ -1319,8 +1589,9 @@ fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t s
 {
     if (t.nrefresh == 0) return FS_OK;
     TimedLaunch timed(1);
-    launch_timed(k_refresh, dim3(t.nrefresh), dim3(kBlock), (uint32_t)refresh_lds_bytes(c.Kmax), s,
-                 timed.start(), timed.stop(), t.desc, t.refresh, step);
+    launch_timed(refresh_kernel(c), dim3(t.nrefresh), dim3(kBlock),
+                 (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), t.desc,
+                 t.refresh, step);
     FS_HIP(hipGetLastError());
     timed.used();
     return FS_OK;
@@ -1333,7 +1604,10 @@ fs_status engine_outputs(const EngineTables &t, const EngineConfig &c, fs_score 
     k_outputs<<<t.ninst, kBlock, 0, s>>>(t.desc, scores, errors);
     FS_HIP(hipGetLastError());
     if (t.nrefresh > 0) {
-        k_assign<<<t.nrefresh, kBlock, 0, s>>>(t.desc, t.refresh);
+        if (c.refresh_mpt == kBlock)
+            k_assign<kBlock><<<t.nrefresh, kBlock, 0, s>>>(t.desc, t.refresh);
+        else
+            k_assign<kRefreshMissions><<<t.nrefresh, kBlock, 0, s>>>(t.desc, t.refresh);
         FS_HIP(hipGetLastError());
     }
     return FS_OK;

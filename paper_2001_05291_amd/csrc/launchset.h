@@ -19,6 +19,13 @@ struct InstSpec {
     int32_t *assign_out = nullptr;
     int32_t *sc_cov = nullptr;
     int64_t *sc_dist = nullptr;
+    // heterogeneous fleet (typed = false: homogeneous)
+    bool typed = false;
+    int32_t K_r = 0;
+    const int32_t *base_hel = nullptr;   // device B
+    const int32_t *rho = nullptr;        // device M, or NULL
+    const int32_t *init_rot = nullptr;   // device K (with init_host), or NULL
+    int32_t *best_rot_out = nullptr;     // device K, or NULL
 };
 
 struct LaunchSet {
@@ -31,6 +38,7 @@ struct LaunchSet {
     int nrank_rows = 0;
     int32_t Bmax = 0;
     bool any_rank = false;
+    bool any_typed = false;
     fs_score *d_scores = nullptr;
     int32_t *d_errors = nullptr;
     LaunchSet() = default;

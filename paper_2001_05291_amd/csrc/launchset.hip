@@ -54,6 +54,12 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     cfg.nt = env_int("FS_SWEEP_NT", table_bytes > ((size_t)96 << 20)) != 0;
     cfg.queue = env_int("FS_SWEEP_QUEUE", 1) != 0;
     cfg.Kmax = Kmax;
+    cfg.typed = false;
+    for (const InstSpec &p : specs) cfg.typed = cfg.typed || p.typed;
+    if (cfg.typed) {   // the one typed form: queued, one load in flight
+        cfg.U = 1;
+        cfg.queue = true;
+    }
     ls.Bmax = Bmax;
 
     std::vector<InstPlan> plans(n);
@@ -63,14 +69,22 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
         Mp[i] = (specs[i].M + 3) / 4 * 4;
     }
     std::vector<Tile> sweep, score, refresh, rank_rows;
-    build_tiles(plans, Mp, sweep, score, refresh);
+    // small K over many missions: a thread per mission scanning every open
+    // slot gives a quarter of the refresh workgroups (each re-derives the
+    // move, so fewer of them is cheaper)
+    int64_t refresh64 = 0;
+    for (int i = 0; i < n; ++i) refresh64 += (Mp[i] + kRefreshMissions - 1) / kRefreshMissions;
+    cfg.refresh_mpt = env_int("FS_REFRESH_WIDE", Kmax <= 32 && refresh64 >= 4096) != 0
+                          ? kBlock : kRefreshMissions;
+    build_tiles(plans, Mp, sweep, score, refresh, cfg.refresh_mpt);
     // few long row groups: 1024-thread workgroups keep four times as many
     // waves in flight, so each thread has fewer dependent load rounds
     std::vector<int32_t> chunks(n);
     for (int i = 0; i < n; ++i) chunks[i] = plans[i].chunk;
     std::sort(chunks.begin(), chunks.end());
     cfg.wide = env_int("FS_SWEEP_WIDE", cfg.J <= 2 && sweep.size() < 1024 &&
-                                            chunks[n / 2] >= 8192) != 0 && cfg.J <= 2;
+                                            chunks[n / 2] >= 8192) != 0 && cfg.J <= 2 &&
+               !cfg.typed;
     size_t list_ints = 0;
     for (int i = 0; i < n; ++i) {
         if (specs[i].init_host) {
@@ -123,6 +137,13 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
         d.sc_dist = p.sc_dist;
         d.best_out = p.best_out;
         d.assign_out = p.assign_out;
+        d.typed = p.typed ? 1 : 0;
+        d.K_r = p.typed ? p.K_r : p.K;
+        d.base_hel = p.base_hel;
+        d.rho = p.rho;
+        d.init_rot = p.init_rot;
+        d.best_rot_out = p.best_rot_out;
+        ls.any_typed = ls.any_typed || p.typed;
         if (p.init_host) {
             d.need_rank = 0;
             d.sums = nullptr;
@@ -206,7 +227,7 @@ bool user_fixed_sweep()
 // The fastest is kept for this shape for the rest of the process.
 fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
 {
-    if (!ls.cfg.vec4 || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
+    if (!ls.cfg.vec4 || ls.cfg.typed || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
         env_int("FS_AUTOTUNE", 1) == 0)
         return FS_OK;
     TuneKey key{ls.tabs.ninst, ls.tabs.nsweep, ls.tabs.nscore, 0, 0,
@@ -293,6 +314,7 @@ fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s)
 {
     FS_TRY(engine_reset(ls.tabs, ls.Bmax, ls.cfg.Kmax, s));
     if (ls.any_rank) FS_TRY(engine_rank_lists(ls.tabs, ls.rank_rows, ls.nrank_rows, ls.Bmax, s));
+    if (ls.any_typed) FS_TRY(engine_fleet_lists(ls.tabs, s));
     FS_TRY(engine_init(ls.tabs, ls.cfg, 0, s));
     if (N >= 1) FS_TRY(tune_sweep(ls, s));
     for (int32_t t = 1; t <= N; ++t) {

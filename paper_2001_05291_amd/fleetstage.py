@@ -65,6 +65,11 @@ class ServeStats(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("running", ctypes.c_int32), ("queued", ctypes.c_int32)]
 
+
+class Fleet(ctypes.Structure):
+    _fields_ = [("rotary", ctypes.c_int32), ("fixed", ctypes.c_int32),
+                ("heliport", ctypes.c_void_p), ("rotary_only", ctypes.c_void_p)]
+
 _lib = None
 
 
@@ -91,6 +96,13 @@ def lib():
     L.fs_tabu_solve.restype = i32
     L.fs_tabu_solve.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(Params), vp, vp,
                                 ctypes.POINTER(Score), vp, vp, vp]
+    L.fs_fleet_move_scores.restype = i32
+    L.fs_fleet_move_scores.argtypes = [vp, i64, i32, i32, ctypes.POINTER(Fleet), vp, vp, i32,
+                                       vp, vp, vp]
+    L.fs_fleet_solve.restype = i32
+    L.fs_fleet_solve.argtypes = [vp, i64, i32, i32, ctypes.POINTER(Fleet),
+                                 ctypes.POINTER(Params), vp, vp, vp, vp, ctypes.POINTER(Score),
+                                 vp, vp, vp]
     L.fs_tabu_solve_batch.restype = i32
     L.fs_tabu_solve_batch.argtypes = [ctypes.POINTER(Instance), i32, ctypes.POINTER(Params),
                                       ctypes.POINTER(Score), vp]
@@ -286,6 +298,81 @@ def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
         res.append(SolveResult(best, int(scores[i].coverage), int(scores[i].distance),
                                int(scores[i].best_iter), assign, tr))
     return res
+
+
+# ---------------------------------------------------------------- heterogeneous fleet
+
+
+def _fleet(K_r, K_f, heliport, rotary_only, dev, B, M):
+    hel = torch.as_tensor(heliport).to(device=dev, dtype=torch.int32).contiguous()
+    if hel.numel() != B:
+        raise ValueError(f"heliport flags: expected {B}, got {hel.numel()}")
+    rho = None
+    if rotary_only is not None:
+        rho = torch.as_tensor(rotary_only).to(device=dev, dtype=torch.int32).contiguous()
+        if rho.numel() != M:
+            raise ValueError(f"rotary-only flags: expected {M}, got {rho.numel()}")
+    f = Fleet(int(K_r), int(K_f), hel.data_ptr(), rho.data_ptr() if rho is not None else None)
+    return f, (hel, rho)
+
+
+def fleet_move_scores(C, K_r: int, K_f: int, heliport, rotary_only, open_ids, rotary,
+                      range_m: int, M: int | None = None, stream=None):
+    """(cov, dist) device tensors K x B: value of the placement with the vehicle
+    of slot k moved to base j; -1 where j is occupied or a heliport the vehicle
+    cannot use."""
+    B, M, ldc = _table(C, M)
+    dev = C.device
+    f, keep = _fleet(K_r, K_f, heliport, rotary_only, dev, B, M)
+    op = torch.as_tensor(open_ids).to(device=dev, dtype=torch.int32).contiguous()
+    rt = torch.as_tensor(rotary).to(device=dev, dtype=torch.int32).contiguous()
+    K = int(K_r) + int(K_f)
+    if op.numel() != K or rt.numel() != K:
+        raise ValueError(f"placement and types must hold K={K} entries")
+    cov = torch.empty((K, B), dtype=torch.int32, device=dev)
+    dist = torch.empty((K, B), dtype=torch.int64, device=dev)
+    _check(lib().fs_fleet_move_scores(_table_ptr(C), ldc, B, M, ctypes.byref(f), _ptr(op),
+                                      _ptr(rt), int(range_m), _ptr(cov), _ptr(dist),
+                                      _stream(stream)))
+    return cov, dist
+
+
+@dataclass
+class FleetResult(SolveResult):
+    best_rotary: torch.Tensor = None   # device int32 K: types of best_open (1 = rotary-wing)
+
+
+def fleet_solve(C, K_r: int, K_f: int, heliport, rotary_only, range_m: int, tenure: int,
+                iterations: int, mode: int = 0, init_open=None, init_rotary=None,
+                M: int | None = None, want_assign: bool = True, want_trace: bool = True,
+                stream=None) -> FleetResult:
+    """Typed Tabu / local search over vehicle relocations (heterogeneous fleet)."""
+    B, M, ldc = _table(C, M)
+    dev = C.device
+    f, keep = _fleet(K_r, K_f, heliport, rotary_only, dev, B, M)
+    K = int(K_r) + int(K_f)
+    p = Params(int(tenure), int(iterations), int(range_m), int(mode))
+    best = torch.empty(K, dtype=torch.int32, device=dev)
+    brot = torch.empty(K, dtype=torch.int32, device=dev)
+    assign = torch.empty(M, dtype=torch.int32, device=dev) if want_assign else None
+    n = max(int(iterations), 0)
+    trace = torch.empty(max(n, 1) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=dev) \
+        if want_trace else None
+    init = irot = None
+    if init_open is not None:
+        init = torch.as_tensor(init_open).to(device=dev, dtype=torch.int32).contiguous()
+        if init_rotary is not None:
+            irot = torch.as_tensor(init_rotary).to(device=dev, dtype=torch.int32).contiguous()
+    sc = Score()
+    _check(lib().fs_fleet_solve(_table_ptr(C), ldc, B, M, ctypes.byref(f), ctypes.byref(p),
+                                _ptr(init), _ptr(irot), _ptr(best), _ptr(brot),
+                                ctypes.byref(sc), _ptr(assign),
+                                _ptr(trace) if n > 0 else None, _stream(stream)))
+    tr = None
+    if want_trace:
+        tr = trace[: n * TRACE_DTYPE.itemsize].cpu().numpy().view(TRACE_DTYPE)
+    return FleetResult(best, int(sc.coverage), int(sc.distance), int(sc.best_iter), assign, tr,
+                       brot)
 
 
 def timing_enable(on: bool = True, every: int = 1) -> None:

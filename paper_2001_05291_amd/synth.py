@@ -50,6 +50,7 @@ _S_SIZES = 12
 _S_PERTURB_PICK, _S_PERTURB_NEW = 13, 14
 _S_ARRIVAL, _S_REQ_KIND, _S_REQ_PICK = 15, 16, 17
 _S_POOL_RANGE = 18
+_S_HELIPORT, _S_HOSP_ROTARY = 19, 20
 
 
 def _mix64(z: np.ndarray) -> np.ndarray:
@@ -189,6 +190,11 @@ WORKLOADS = {
     "medium": dict(seed=0, B=500, H=1_500, M=20_000, K=30, R=1_000_000, T=15, N=500),
     "large": dict(seed=0, B=4_000, H=10_000, M=100_000, K=64, R=900_000, T=25, N=200),
 }
+# Heterogeneous fleet (Section 3 sets R and F, Eq. 10): a share of the
+# candidate bases are heliports, a share of the hospitals can be reached by
+# rotary-wing vehicles only (a mission touching one is rotary-only), and a
+# share of the K vehicles are rotary-wing.
+FLEET = dict(heliport_fraction=0.4, hospital_rotary_fraction=0.25, rotary_fraction=0.6)
 BATCH = dict(n=1024, size_seed=4, T=10, N=200)
 # Repositioning requests: 95% on instances shaped like the ragged batch, 5% on
 # large ones; each redraws 10% of the missions and runs 100 iterations.
@@ -259,3 +265,23 @@ def request_stream(n: int, rate: float, n_small: int, n_large: int, seed: int = 
     small_idx = np.minimum(np.floor(n_small * u).astype(np.int64), max(n_small - 1, 0))
     large_idx = n_small + np.minimum(np.floor(n_large * u).astype(np.int64), max(n_large - 1, 0))
     return t, np.where(large, large_idx, small_idx)
+
+
+def fleet_flags(seed: int, B: int, mission_ph: np.ndarray, H: int,
+                heliport_fraction: float = FLEET["heliport_fraction"],
+                hospital_rotary_fraction: float = FLEET["hospital_rotary_fraction"]):
+    """(heliport (B,) int32, rotary_only (M,) int32): base b is a heliport with
+    probability heliport_fraction; a hospital is reachable by rotary-wing
+    vehicles only with probability hospital_rotary_fraction, and a mission is
+    rotary-only when its pickup or its delivery hospital is."""
+    hel = (uniform(seed, _S_HELIPORT, np.arange(B)) < heliport_fraction).astype(np.int32)
+    hosp = uniform(seed, _S_HOSP_ROTARY, np.arange(H)) < hospital_rotary_fraction
+    ph = np.asarray(mission_ph)
+    rho = (hosp[ph[:, 0]] | hosp[ph[:, 1]]).astype(np.int32)
+    return hel, rho
+
+
+def fleet_split(K: int, rotary_fraction: float = FLEET["rotary_fraction"]):
+    """(K_r, K_f) with K_r = round(rotary_fraction * K)."""
+    K_r = int(np.floor(rotary_fraction * K + 0.5))
+    return K_r, K - K_r

@@ -25,6 +25,7 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     names = declared_symbols()
     for required in ("fs_build_cost_table", "fs_rank_bases", "fs_move_scores", "fs_tabu_solve",
+                     "fs_tabu_solve_batch", "fs_fleet_move_scores", "fs_fleet_solve",
                      "fs_last_error", "fs_version"):
         assert required in names
 
@@ -67,3 +68,20 @@ def test_server_config_validated_before_device_use(library):
     for cfg in (Cfg(1 << 30, 0, 0, 0.0, 3, 0), Cfg(0, 4, 0, 0.0, 3, 0),
                 Cfg(1 << 30, 4, 0, 0.0, 5, 0), Cfg(1 << 30, 4, -1, 0.0, 3, 0)):
         assert library.fs_serve_open(ctypes.byref(cfg), ctypes.byref(h)) == -1
+
+
+def test_fleet_calls_validated_before_device_use(library):
+    vp = ctypes.c_void_p
+    library.fs_fleet_solve.restype = ctypes.c_int32
+    library.fs_fleet_solve.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32] + \
+        [vp] * 10
+    assert library.fs_fleet_solve(None, 10, 5, 10, *([None] * 10)) == -1
+    library.fs_last_error.restype = ctypes.c_char_p
+    assert b"NULL" in library.fs_last_error()
+    library.fs_fleet_move_scores.restype = ctypes.c_int32
+    library.fs_fleet_move_scores.argtypes = [vp, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp,
+                                             vp, vp]
+    assert library.fs_fleet_move_scores(None, 10, 5, 10, None, None, None, 5, None, None,
+                                        None) == -1
+    assert b"fleet" in library.fs_last_error()

@@ -27,7 +27,9 @@ def same(a, b):
     assert np.array_equal(a.assign.cpu().numpy(), b.assign.cpu().numpy())
 
 
-def test_batch_random_ragged_matches_solo_and_oracle(fs):
+@pytest.mark.parametrize("refresh_wide", ["0", "1"])
+def test_batch_random_ragged_matches_solo_and_oracle(fs, monkeypatch, refresh_wide):
+    monkeypatch.setenv("FS_REFRESH_WIDE", refresh_wide)
     rng = np.random.default_rng(71)
     items, hosts = [], []
     for i in range(40):

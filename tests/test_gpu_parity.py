@@ -137,20 +137,21 @@ def test_move_scores_small_and_medium():
 
 
 # (rows per workgroup, mission chunks, loads in flight, non-temporal loads,
-#  queued scoring, 1024-thread workgroups)
-GEOMETRIES = [(1, 1, 1, 1, 1, 0), (2, 3, 2, 0, 0, 0), (4, 1, 4, 1, 1, 0), (8, 5, 1, 1, 1, 0),
-              (1, 7, 4, 0, 1, 1), (2, 1, 4, 1, 1, 1), (4, 2, 2, 1, 0, 0), (1, 1, 2, 1, 0, 1),
-              (2, 2, 1, 1, 0, 1)]
+#  queued scoring, 1024-thread sweep workgroups, one mission per refresh thread)
+GEOMETRIES = [(1, 1, 1, 1, 1, 0, 0), (2, 3, 2, 0, 0, 0, 1), (4, 1, 4, 1, 1, 0, 0),
+              (8, 5, 1, 1, 1, 0, 1), (1, 7, 4, 0, 1, 1, 0), (2, 1, 4, 1, 1, 1, 1),
+              (4, 2, 2, 1, 0, 0, 0), (1, 1, 2, 1, 0, 1, 1), (2, 2, 1, 1, 0, 1, 0),
+              (4, 1, 1, 1, 0, 1, 1), (8, 1, 1, 0, 0, 1, 0)]
 
 
-@pytest.mark.parametrize("J,split,U,nt,q,w", GEOMETRIES)
-def test_move_scores_launch_geometries(J, split, U, nt, q, w):
+@pytest.mark.parametrize("J,split,U,nt,q,w,rw", GEOMETRIES)
+def test_move_scores_launch_geometries(J, split, U, nt, q, w, rw):
     inst = synth.make_instance(seed=31, B=90, H=200, M=4103)
     C = oracle_table(inst)
     rng = np.random.default_rng(J * 10 + split)
     S = rng.choice(90, 11, replace=False).tolist()
     with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt,
-             FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w):
+             FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w, FS_REFRESH_WIDE=rw):
         check_scores(C, S, 1_000_000, ldc=4104)   # 16-byte rows
         check_scores(C, S, 1_000_000)             # 4-byte rows (ldc % 4 != 0)
 
@@ -279,11 +280,13 @@ def test_plans_are_bit_identical():
     _, C = instance_and_table("medium")
     Cd = padded_table(C, c["M"])
     ref = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
-    for J, split, U, nt, q, w in ((1, 1, 1, 1, 1, 0), (2, 4, 2, 0, 0, 0), (4, 9, 4, 1, 1, 0),
-                                  (8, 2, 1, 0, 1, 0), (4, 1, 2, 1, 0, 0), (1, 3, 4, 1, 1, 1),
-                                  (1, 1, 4, 0, 0, 1), (2, 1, 2, 1, 1, 1)):
+    for J, split, U, nt, q, w, rw in ((1, 1, 1, 1, 1, 0, 0), (2, 4, 2, 0, 0, 0, 1),
+                                      (4, 9, 4, 1, 1, 0, 0), (8, 2, 1, 0, 1, 0, 1),
+                                      (4, 1, 2, 1, 0, 0, 1), (1, 3, 4, 1, 1, 1, 0),
+                                      (1, 1, 4, 0, 0, 1, 1), (2, 1, 2, 1, 1, 1, 0),
+                                      (4, 1, 1, 1, 0, 1, 1)):
         with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_U=U, FS_SWEEP_NT=nt,
-                 FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w):
+                 FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w, FS_REFRESH_WIDE=rw):
             g = fs.tabu_solve(Cd, c["K"], c["R"], c["T"], 60)
         assert np.array_equal(g.trace, ref.trace)
         assert np.array_equal(g.best_open.cpu().numpy(), ref.best_open.cpu().numpy())

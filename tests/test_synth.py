@@ -60,3 +60,22 @@ def test_serve_pool_shapes():
     assert all(w.B == synth.SERVE_LARGE["B"] and w.M == synth.SERVE_LARGE["M"]
                and w.K == synth.SERVE_LARGE["K"] for w in pool[4:])
     assert all(800_000 <= w.R <= 1_400_000 for w in pool)
+
+
+def test_fleet_flags_deterministic_and_consistent():
+    inst = synth.make_instance(seed=7, B=300, H=400, M=3000)
+    hel, rho = synth.fleet_flags(7, inst.B, inst.mission_ph, 400)
+    hel2, rho2 = synth.fleet_flags(7, inst.B, inst.mission_ph, 400)
+    assert np.array_equal(hel, hel2) and np.array_equal(rho, rho2)
+    assert hel.shape == (300,) and rho.shape == (3000,)
+    assert set(np.unique(hel)) <= {0, 1} and set(np.unique(rho)) <= {0, 1}
+    assert 0.3 < hel.mean() < 0.5
+    # P(rotary-only) = 1 - (1 - 0.25)^2 for distinct endpoints
+    assert 0.36 < rho.mean() < 0.51
+    # a hospital on a mission that either type may fly is not rotary-only, so
+    # a rotary-only mission has at least one endpoint outside that set
+    ph = inst.mission_ph
+    clear = np.zeros(400, dtype=bool)
+    clear[ph[rho == 0].reshape(-1)] = True
+    assert not np.any(clear[ph[rho == 1, 0]] & clear[ph[rho == 1, 1]])
+    assert synth.fleet_split(30) == (18, 12) and synth.fleet_split(5) == (3, 2)
