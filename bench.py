@@ -12,6 +12,9 @@ scores K*(B-K) swap moves over M missions.  It is reported for the whole step
   roofline      the swap sweep's algorithmic bytes per launch over its average
                 launch time (HIP events on its own stream), against 8 TB/s HBM;
   cpu_baseline  the CPU oracle on a bounded sample of the same search;
+  fleet         the heterogeneous fleet (heliports, rotary-only missions,
+                rotary- and fixed-wing vehicles) on the same workload: the
+                typed relocation search's solves/s and its sweep roofline;
   batch         the ragged batch (1,024 instances of uneven size, 200
                 iterations each): solves/s of one launch set against one solve
                 per instance, results identical;
@@ -65,6 +68,8 @@ def main():
     ap.add_argument("--serve-pool", default="1024,64",
                     help="resident instances of the repositioning load: small,large")
     ap.add_argument("--serve-slots", type=int, default=128)
+    ap.add_argument("--no-fleet", action="store_true",
+                    help="skip the heterogeneous-fleet leg (typed relocation search)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the ragged-batch leg (one launch set vs one solve per instance)")
     args = ap.parse_args()
@@ -151,6 +156,11 @@ def main():
                          f"(oracle cost table, not timed); {cpu_s:.2f} s"}
         log(f"[bench] cpu baseline {cpu['value']:.3e} MM-evals/s on {cpu['cores']} threads")
 
+    fleet = None
+    if not args.no_fleet:
+        from paper_2001_05291_amd import fleetbench
+        fleet = fleetbench.run(fs, torch, workload=args.workload, log=log)
+
     batch = None
     if not args.no_batch:
         from paper_2001_05291_amd import batchbench
@@ -184,6 +194,7 @@ def main():
                    "seed": c["seed"], "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fleet": fleet,
         "batch": batch,
         "serve": serve,
         "detail": {"sweep_ms_per_launch": sweep_ms / max(sweep_n, 1),

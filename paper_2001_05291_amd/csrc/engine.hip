@@ -95,16 +95,24 @@ __device__ __forceinline__ Candidate shfl_xor_cand(const Candidate &c, int off)
     return o;
 }
 
+// Best candidate of the wave under the move order (a total order, so the
+// result does not depend on the reduction order); the same in every lane.
+__device__ __forceinline__ Candidate wave_best(Candidate c)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const Candidate o = shfl_xor_cand(c, off);
+        if (cand_better(o, c)) c = o;
+    }
+    return c;
+}
+
 // Best candidate of the workgroup under the move order (a total order, so the
 // result does not depend on the reduction order); valid in every thread.
 template <int BS = kBlock>
 __device__ Candidate block_best(Candidate c, Candidate *s_red /* BS/64 + 1 */)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        Candidate o = shfl_xor_cand(c, off);
-        if (cand_better(o, c)) c = o;
-    }
+    c = wave_best(c);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) s_red[wave] = c;
@@ -800,11 +808,7 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
         }
     }
     if (one_wave) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const Candidate o = shfl_xor_cand(mine, off);
-            if (cand_better(o, mine)) mine = o;
-        }
+        mine = wave_best(mine);
     } else {
         mine = block_best<BS>(mine, s_red);
     }
@@ -863,21 +867,125 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
 // Elements with c < b2 are a few percent of the table (about 2 / (K + 1) for
 // scattered bases), but with one wave per 64 missions nearly every wave has a
 // lane that takes the scoring branch, so scoring in place costs every element
-// the branch's full instruction count.  This variant only compares in the
-// streaming loop: each wave appends the lanes that hit (c, b1, b2, o1) to a
-// queue in LDS, one queue per row, and scores 64 queued elements at a time
-// with every lane busy.  The loop runs in whole waves (lanes past the end of
-// the chunk load sentinels that never hit), so queue lengths are wave-uniform
-// and live in scalar registers; a wave only reads entries it wrote itself, so
-// no workgroup barrier is involved.
+// the branch's full instruction count.  The queued variants only compare in
+// the streaming loop: each wave appends the lanes that hit to a queue in LDS,
+// one queue per row, and scores 64 queued elements at a time with every lane
+// busy.  The loop runs in whole waves (lanes past the end of the chunk load
+// sentinels that never hit), so queue lengths are wave-uniform and live in
+// scalar registers; a wave only reads entries it wrote itself, so no
+// workgroup barrier is involved.
 constexpr int kQueue = 128;   // entries per (wave, row): below 64 + 64 before a drain
 
+// One row per workgroup: the loop streams the row and b2 alone, queues
+// (c, mission), and gathers b1, b2 and o1 of the 64 queued missions when it
+// scores them (a few percent of the missions, so b1 and o1 are not streamed).
 struct QueueRow {
+    int32_t c[kQueue], m[kQueue];
+};
+
+template <int NC>
+__device__ __forceinline__ void visit_queued(const InstDesc &d, const QueueRow &qr, int32_t at,
+                                             int32_t R, int32_t *t1c, int64_t *t1d,
+                                             int32_t *__restrict__ bc, u64 *__restrict__ bd)
+{
+    const int32_t c = qr.c[at], m = qr.m[at];
+    const int32_t b1 = d.b1[m], b2 = d.b2[m], o1 = d.o1[m];
+    const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
+    const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+    visit<NC>(c, b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
+}
+
+template <int BS, int J, int U, bool NT, int NC>
+__device__ __forceinline__ void sweep_vec4_queued1(const InstDesc &d, const int32_t *jrow,
+                                                  int32_t m0, int32_t m1, int32_t *t1c,
+                                                  int64_t *t1d, int32_t *bc, u64 *bd)
+{
+    __shared__ QueueRow s_q[BS / 64][J];
+    const int32_t K = d.K, R = d.R;
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    gv4i *b2v = (gv4i *)d.b2;
+    gv4i *rows[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) rows[r] = (gv4i *)(d.C + (int64_t)jrow[r] * d.ldc);
+    int32_t len[J];
+#pragma unroll
+    for (int r = 0; r < J; ++r) len[r] = 0;
+    const int32_t qend = m1 >> 2;
+    for (int32_t qw = (m0 >> 2) + wave * 64; qw < qend; qw += U * BS) {
+        // lanes past the end re-read the last quad and never hit (b2 = INT32_MIN)
+        v4i cv[U][J], vb2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t q = min(qw + u * BS + lane, qend - 1);
+#pragma unroll
+            for (int r = 0; r < J; ++r)
+                cv[u][r] = NT ? __builtin_nontemporal_load(rows[r] + q) : rows[r][q];
+            vb2[u] = b2v[q];
+        }
+        // keep every load of the iteration ahead of the first use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (qw + u * BS + lane >= qend) vb2[u] = (v4i)(INT32_MIN);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int r = 0; r < J; ++r) {
+                    const bool hit = cv[u][r][e] < vb2[u][e];
+                    const u64 mask = __builtin_amdgcn_ballot_w64(hit);
+                    if (mask == 0) continue;
+                    QueueRow &qr = s_q[wave][r];
+                    if (hit) {
+                        const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(mask >> 32),
+                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)len[r]));
+                        qr.c[at] = cv[u][r][e];
+                        qr.m[at] = 4 * (qw + u * BS + lane) + e;
+                    }
+                    len[r] = __builtin_amdgcn_readfirstlane(len[r] +
+                                                            (int32_t)__builtin_popcountll(mask));
+                    if (len[r] >= 64) {
+                        // score the oldest 64, then move the rest (at most 63) down
+                        __builtin_amdgcn_wave_barrier();
+                        visit_queued<NC>(d, qr, lane, R, t1c + NC * r, t1d + NC * r,
+                                         bc + r * K, bd + r * K);
+                        len[r] -= 64;
+                        int32_t c = 0, mm = 0;
+                        if (lane < len[r]) {
+                            c = qr.c[64 + lane];
+                            mm = qr.m[64 + lane];
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane < len[r]) {
+                            qr.c[lane] = c;
+                            qr.m[lane] = mm;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < J; ++r)
+        if (lane < len[r])
+            visit_queued<NC>(d, s_q[wave][r], lane, R, t1c + NC * r, t1d + NC * r,
+                             bc + r * K, bd + r * K);
+}
+
+// Several rows per workgroup: the rows share one streamed copy of b1, b2 and
+// o1, and each queue entry carries the element with its state.
+struct QueueRow4 {
     int32_t c[kQueue], b1[kQueue], b2[kQueue], o1[kQueue];
 };
 
 template <int NC>
-__device__ __forceinline__ void visit_queued(const QueueRow &qr, int32_t at, int32_t R,
+__device__ __forceinline__ void visit_queued4(const QueueRow4 &qr, int32_t at, int32_t R,
                                              int32_t *t1c, int64_t *t1d, int32_t *__restrict__ bc,
                                              u64 *__restrict__ bd)
 {
@@ -888,11 +996,11 @@ __device__ __forceinline__ void visit_queued(const QueueRow &qr, int32_t at, int
 }
 
 template <int BS, int J, int U, bool NT, int NC>
-__device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32_t *jrow,
+__device__ __forceinline__ void sweep_vec4_queued4(const InstDesc &d, const int32_t *jrow,
                                                   int32_t m0, int32_t m1, int32_t *t1c,
                                                   int64_t *t1d, int32_t *bc, u64 *bd)
 {
-    __shared__ QueueRow s_q[BS / 64][J];
+    __shared__ QueueRow4 s_q[BS / 64][J];
     const int32_t K = d.K, R = d.R;
     const int32_t lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -934,7 +1042,7 @@ __device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32
                     const bool hit = cv[u][r][e] < vb2[u][e];
                     const u64 mask = __builtin_amdgcn_ballot_w64(hit);
                     if (mask == 0) continue;
-                    QueueRow &qr = s_q[wave][r];
+                    QueueRow4 &qr = s_q[wave][r];
                     if (hit) {
                         const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(mask >> 32),
@@ -949,7 +1057,7 @@ __device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32
                     if (len[r] >= 64) {
                         // score the oldest 64, then move the rest (at most 63) down
                         __builtin_amdgcn_wave_barrier();
-                        visit_queued<NC>(qr, lane, R, t1c + NC * r, t1d + NC * r, bc + r * K,
+                        visit_queued4<NC>(qr, lane, R, t1c + NC * r, t1d + NC * r, bc + r * K,
                                          bd + r * K);
                         len[r] -= 64;
                         int32_t c = 0, b1 = 0, b2 = 0, o1 = 0;
@@ -976,8 +1084,22 @@ __device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32
 #pragma unroll
     for (int r = 0; r < J; ++r)
         if (lane < len[r])
-            visit_queued<NC>(s_q[wave][r], lane, R, t1c + NC * r, t1d + NC * r, bc + r * K,
+            visit_queued4<NC>(s_q[wave][r], lane, R, t1c + NC * r, t1d + NC * r, bc + r * K,
                              bd + r * K);
+}
+
+
+// Gathering per row pays off for one row; with several, each row's hits would
+// gather on their own.
+template <int BS, int J, int U, bool NT, int NC>
+__device__ __forceinline__ void sweep_vec4_queued(const InstDesc &d, const int32_t *jrow,
+                                                  int32_t m0, int32_t m1, int32_t *t1c,
+                                                  int64_t *t1d, int32_t *bc, u64 *bd)
+{
+    if constexpr (J == 1)
+        sweep_vec4_queued1<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, bc, bd);
+    else
+        sweep_vec4_queued4<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, bc, bd);
 }
 
 template <int BS, int J, int NC>
@@ -1294,7 +1416,7 @@ fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t s
         // 1024-thread workgroups: up to 2 rows with any variant; more rows
         // only with in-place scoring and one load in flight (LDS queues and
         // registers grow with the rows)
-        if constexpr (NC == 1 && (J <= 2 || (!Q && U == 1))) {
+        if constexpr (J <= 2 || (!Q && U == 1)) {
             if (c.wide) {
                 launch_timed(k_sweep<kWideBlock, J, U, VEC4, NT, Q, NC>, dim3(t.nsweep),
                              dim3(kWideBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
@@ -1329,15 +1451,18 @@ fs_status launch_sweep_ju(const EngineTables &t, const EngineConfig &c, int32_t 
                 : launch_sweep_t<J, U, true, false, false, 1>(t, c, step, s, tm);
 }
 
-// Typed launch sets: the queued variant (one load in flight, 256-thread
-// workgroups) or the scalar one.
+// Typed launch sets: one load in flight (U = 1), queued or in place, or the
+// scalar variant.
 template <int J>
 fs_status launch_sweep_typed(const EngineTables &t, const EngineConfig &c, int32_t step,
                              hipStream_t s, TimedLaunch &tm)
 {
     if (!c.vec4) return launch_sweep_t<J, 1, false, false, false, 2>(t, c, step, s, tm);
-    return c.nt ? launch_sweep_t<J, 1, true, true, true, 2>(t, c, step, s, tm)
-                : launch_sweep_t<J, 1, true, false, true, 2>(t, c, step, s, tm);
+    if (c.queue)
+        return c.nt ? launch_sweep_t<J, 1, true, true, true, 2>(t, c, step, s, tm)
+                    : launch_sweep_t<J, 1, true, false, true, 2>(t, c, step, s, tm);
+    return c.nt ? launch_sweep_t<J, 1, true, true, false, 2>(t, c, step, s, tm)
+                : launch_sweep_t<J, 1, true, false, false, 2>(t, c, step, s, tm);
 }
 
 template <int J>

@@ -56,10 +56,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     cfg.Kmax = Kmax;
     cfg.typed = false;
     for (const InstSpec &p : specs) cfg.typed = cfg.typed || p.typed;
-    if (cfg.typed) {   // the one typed form: queued, one load in flight
-        cfg.U = 1;
-        cfg.queue = true;
-    }
+    if (cfg.typed) cfg.U = 1;   // typed sweeps keep one load in flight
     ls.Bmax = Bmax;
 
     std::vector<InstPlan> plans(n);
@@ -82,9 +79,9 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     std::vector<int32_t> chunks(n);
     for (int i = 0; i < n; ++i) chunks[i] = plans[i].chunk;
     std::sort(chunks.begin(), chunks.end());
+    // (forms without a 1024-thread kernel launch 256 threads)
     cfg.wide = env_int("FS_SWEEP_WIDE", cfg.J <= 2 && sweep.size() < 1024 &&
-                                            chunks[n / 2] >= 8192) != 0 && cfg.J <= 2 &&
-               !cfg.typed;
+                                            chunks[n / 2] >= 8192) != 0;
     size_t list_ints = 0;
     for (int i = 0; i < n; ++i) {
         if (specs[i].init_host) {
@@ -195,12 +192,12 @@ namespace {
 // Shape of a launch set as far as the sweep's speed is concerned.
 struct TuneKey {
     int64_t ninst, nsweep, nscore, rows, missions;
-    int32_t J, Kmax, vec4, nt;
+    int32_t J, Kmax, vec4, nt, typed;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(ninst, nsweep, nscore, rows, missions, J, Kmax, vec4, nt) <
+        return std::tie(ninst, nsweep, nscore, rows, missions, J, Kmax, vec4, nt, typed) <
                std::tie(o.ninst, o.nsweep, o.nscore, o.rows, o.missions, o.J, o.Kmax, o.vec4,
-                        o.nt);
+                        o.nt, o.typed);
     }
 };
 
@@ -227,11 +224,11 @@ bool user_fixed_sweep()
 // The fastest is kept for this shape for the rest of the process.
 fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
 {
-    if (!ls.cfg.vec4 || ls.cfg.typed || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
+    if (!ls.cfg.vec4 || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
         env_int("FS_AUTOTUNE", 1) == 0)
         return FS_OK;
     TuneKey key{ls.tabs.ninst, ls.tabs.nsweep, ls.tabs.nscore, 0, 0,
-                ls.cfg.J, ls.cfg.Kmax, ls.cfg.vec4, ls.cfg.nt};
+                ls.cfg.J, ls.cfg.Kmax, ls.cfg.vec4, ls.cfg.nt, ls.cfg.typed};
     for (const InstDesc &d : ls.descs) {
         key.rows += d.nclosed;
         key.missions += d.Mp;
@@ -251,6 +248,7 @@ fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
         for (int q = 0; q < 2; ++q)
             for (int w = 0; w < 2; ++w) {
                 if (w && ls.cfg.J > 2 && (q || U != 1)) continue;   // no such wide form
+                if (ls.cfg.typed && U != 1) continue;                // typed: U = 1 only
                 EngineConfig c = ls.cfg;
                 c.U = U;
                 c.queue = q != 0;

@@ -84,18 +84,21 @@ def test_fleet_move_scores_random_placements():
         check_move_scores(C, hel, rho, S, types, 800_000)
 
 
-# (rows per workgroup, mission chunks, non-temporal loads, one mission per
-#  refresh thread); the typed sweep is always the queued form
-GEOMETRIES = [(1, 1, 1, 0), (2, 3, 0, 1), (4, 1, 1, 0), (8, 5, 1, 1), (1, 7, 0, 1),
-              (4, 2, 1, 0)]
+# (rows per workgroup, mission chunks, non-temporal loads, queued scoring,
+#  1024-thread sweep workgroups, one mission per refresh thread); typed
+#  sweeps keep one load in flight
+GEOMETRIES = [(1, 1, 1, 1, 0, 0), (2, 3, 0, 0, 0, 1), (4, 1, 1, 1, 0, 0), (8, 5, 1, 1, 0, 1),
+              (1, 7, 0, 1, 1, 1), (4, 2, 1, 0, 0, 0), (1, 1, 1, 0, 1, 0), (2, 1, 0, 1, 1, 1),
+              (4, 1, 1, 0, 1, 0), (8, 1, 0, 0, 1, 1)]
 
 
-@pytest.mark.parametrize("J,split,nt,rw", GEOMETRIES)
-def test_fleet_move_scores_launch_geometries(J, split, nt, rw):
+@pytest.mark.parametrize("J,split,nt,q,w,rw", GEOMETRIES)
+def test_fleet_move_scores_launch_geometries(J, split, nt, q, w, rw):
     C, hel, rho = typed_instance(31, B=90, H=200, M=4103)
     rng = np.random.default_rng(J * 10 + split)
     S, types = random_placement(rng, 90, 6, 5, hel)
-    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_NT=nt, FS_REFRESH_WIDE=rw):
+    with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_NT=nt, FS_SWEEP_QUEUE=q,
+             FS_SWEEP_WIDE=w, FS_REFRESH_WIDE=rw):
         check_move_scores(C, hel, rho, S, types, 1_000_000, ldc=4104)   # 16-byte rows
         check_move_scores(C, hel, rho, S, types, 1_000_000)             # 4-byte rows
 
@@ -156,8 +159,8 @@ def test_fleet_solve_given_placement_and_geometries():
     C, hel, rho = typed_instance(9, B=80, H=200, M=3001)
     rng = np.random.default_rng(9)
     S, types = random_placement(rng, 80, 5, 4, hel)
-    for J, split in ((1, 1), (2, 3), (4, 1), (8, 2)):
-        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split):
+    for J, split, q, w in ((1, 1, 1, 1), (2, 3, 0, 0), (4, 1, 0, 1), (8, 2, 1, 0)):
+        with env(FS_SWEEP_J=J, FS_SWEEP_SPLIT=split, FS_SWEEP_QUEUE=q, FS_SWEEP_WIDE=w):
             g, o = run_both(C, hel, rho, 5, 4, 900_000, 5, 30, init=(S, types), ldc=3004)
         assert_same(g, o, C, rho, 900_000)
 
