@@ -100,6 +100,16 @@ def _load():
                                             _i32p, _i32p, _c.POINTER(i32), _c.POINTER(i64),
                                             _c.POINTER(i64)]
     lib.fso_fleet_brute_optimum.restype = None
+    u64 = _c.c_uint64
+    lib.fso_mix64.argtypes = [u64]
+    lib.fso_mix64.restype = u64
+    lib.fso_perm_priority.argtypes = [u64, i32, i32, i32, i32]
+    lib.fso_perm_priority.restype = u64
+    lib.fso_perm_search.argtypes = [_i32p, i64, i32, i32, i32, i32, i32, i32, i32, u64, n_i32,
+                                    _i32p, _c.POINTER(i32), _c.POINTER(i64), _c.POINTER(i32),
+                                    _c.POINTER(i32), n_i32, n_i32, n_i32, n_i32, n_i64, n_i32,
+                                    n_i64]
+    lib.fso_perm_search.restype = _c.c_int
     _lib = lib
     return lib
 
@@ -341,3 +351,48 @@ def fleet_brute_optimum(C, K_r: int, K_f: int, heliport, rotary_only, R: int):
                                     _flags(rotary_only, M), int(R), best, brot, _c.byref(cov),
                                     _c.byref(dist), _c.byref(n))
     return best[:K], brot[:K], int(cov.value), int(dist.value), int(n.value)
+
+
+# ---------------------------------------------------------------- permuted searches
+# (Algorithms 2 and 3 with their random scan orders; readings in perm_oracle.c)
+
+def mix64(z: int) -> int:
+    """SplitMix64 output function."""
+    return int(_load().fso_mix64(int(z) & (2**64 - 1)))
+
+
+def perm_priority(seed: int, p: int, B: int, i: int, j: int) -> int:
+    """Priority of swap (i out, j in) in pass p of a search seeded with seed."""
+    return int(_load().fso_perm_priority(int(seed) & (2**64 - 1), int(p), int(B), int(i), int(j)))
+
+
+@dataclass
+class PermResult(TabuResult):
+    passes: int = 0
+
+
+def perm_search(C, K: int, R: int, T: int, N: int, mode: int, seed: int, init_open=None,
+                M: int | None = None) -> PermResult:
+    """Permuted first-improvement search: mode 2 local search, mode 3 Tabu
+    with improving-only acceptance."""
+    C, B, ldc = _cm(C)
+    M = ldc if M is None else M
+    init = None if init_open is None else np.ascontiguousarray(init_open, dtype=np.int32)
+    best = np.zeros(K, dtype=np.int32)
+    cov = _c.c_int32()
+    dist = _c.c_int64()
+    it = _c.c_int32()
+    passes = _c.c_int32()
+    n = max(int(N), 0)
+    arr = [np.zeros(n, dtype=np.int32) for _ in range(4)]
+    cur_d = np.zeros(n, dtype=np.int64)
+    best_c = np.zeros(n, dtype=np.int32)
+    best_d = np.zeros(n, dtype=np.int64)
+    rc = _load().fso_perm_search(C, ldc, B, M, int(K), int(R), int(T), int(N), int(mode),
+                                 int(seed) & (2**64 - 1), init, best, _c.byref(cov),
+                                 _c.byref(dist), _c.byref(it), _c.byref(passes), arr[0], arr[1],
+                                 arr[2], arr[3], cur_d, best_c, best_d)
+    if rc != 0:
+        raise ValueError("oracle permuted search: invalid arguments")
+    return PermResult(best, int(cov.value), int(dist.value), int(it.value), arr[0], arr[1],
+                      arr[2], arr[3], cur_d, best_c, best_d, int(passes.value))

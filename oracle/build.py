@@ -7,7 +7,8 @@ import subprocess
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(_HERE, "fleetstage_oracle.c"), os.path.join(_HERE, "fleet_oracle.c")]
+SRCS = [os.path.join(_HERE, name)
+        for name in ("fleetstage_oracle.c", "fleet_oracle.c", "perm_oracle.c")]
 OUT = os.path.join(_HERE, "liboracle.so")
 
 
