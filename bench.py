@@ -15,6 +15,9 @@ scores K*(B-K) swap moves over M missions.  It is reported for the whole step
   fleet         the heterogeneous fleet (heliports, rotary-only missions,
                 rotary- and fixed-wing vehicles) on the same workload: the
                 typed relocation search's solves/s and its sweep roofline;
+  portfolio     the paper's permuted local and Tabu searches (random scan
+                orders), ten seeds each in one batch launch: runs/s and the
+                upper / lower / average result;
   batch         the ragged batch (1,024 instances of uneven size, 200
                 iterations each): solves/s of one launch set against one solve
                 per instance, results identical;
@@ -68,6 +71,8 @@ def main():
     ap.add_argument("--serve-pool", default="1024,64",
                     help="resident instances of the repositioning load: small,large")
     ap.add_argument("--serve-slots", type=int, default=128)
+    ap.add_argument("--no-portfolio", action="store_true",
+                    help="skip the seed-portfolio leg (permuted local and Tabu searches)")
     ap.add_argument("--no-fleet", action="store_true",
                     help="skip the heterogeneous-fleet leg (typed relocation search)")
     ap.add_argument("--no-batch", action="store_true",
@@ -161,6 +166,11 @@ def main():
         from paper_2001_05291_amd import fleetbench
         fleet = fleetbench.run(fs, torch, workload=args.workload, log=log)
 
+    portfolio = None
+    if not args.no_portfolio:
+        from paper_2001_05291_amd import portfoliobench
+        portfolio = portfoliobench.run(fs, torch, workload=args.workload, log=log)
+
     batch = None
     if not args.no_batch:
         from paper_2001_05291_amd import batchbench
@@ -195,6 +205,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fleet": fleet,
+        "portfolio": portfolio,
         "batch": batch,
         "serve": serve,
         "detail": {"sweep_ms_per_launch": sweep_ms / max(sweep_n, 1),

@@ -67,12 +67,24 @@ const char *fs_version(void);
  *  mode       0 = Tabu search (Algorithm 3, best admissible move with
  *             aspiration); 1 = local search baseline (Algorithm 2 read as
  *             steepest descent: strictly improving moves only, stop at a local
- *             optimum). */
+ *             optimum); 2 = the paper's permuted local search and 3 = its
+ *             permuted Tabu search (Algorithms 2 and 3 with their random scan
+ *             orders, Section 4.3): each pass scans the swaps in a random
+ *             order drawn from `seed`, continues after the last accepted move
+ *             and accepts the first one that strictly improves the current
+ *             placement (mode 3 skips moves touching a tabu base); a pass
+ *             without acceptance stops the search.  An iteration is one scan
+ *             to the next acceptance or to the end of a pass.  The priority
+ *             of swap (i out, j in) in pass p is
+ *             mix64(mix64(seed + (p + 1) G) + (i B + j + 1) G), with mix64 the
+ *             SplitMix64 output function and G = 0x9E3779B97F4A7C15.
+ *  seed       scan orders of modes 2 and 3 (ignored by modes 0 and 1). */
 typedef struct {
     int32_t tenure;
     int32_t iterations;
     int32_t range_m;
     int32_t mode;
+    uint64_t seed;
 } fs_params;
 
 /* Best placement found: coverage and distance of covered missions, and the
@@ -192,7 +204,8 @@ fs_status fs_fleet_move_scores(const int32_t *C, int64_t ldc, int32_t B, int32_t
                                const int32_t *rotary, int32_t range_m, int32_t *cov_out,
                                int64_t *dist_out, void *stream);
 
-/* Tabu search (mode 0) or local search (mode 1) over vehicle relocations,
+/* Tabu search (mode 0) or local search (mode 1; modes 2 and 3 are
+ * FS_E_INVALID here) over vehicle relocations,
  * exactly as fs_tabu_solve otherwise (tabu list, aspiration, order (cov desc,
  * dist asc, out-base asc, in-base asc), N iterations).  init_open / init_rotary
  * (device, K) give the initial placement and its vehicle types, or init_open =
@@ -217,7 +230,9 @@ fs_status fs_fleet_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M,
  *   init_open      device K ids, or NULL (base ranking)
  *   best_open_out  device K int32, best placement in ascending id order
  *   assign_out     device M int32 (as in fs_tabu_solve), or NULL
- *   trace_out      device p->iterations records, or NULL */
+ *   trace_out      device p->iterations records, or NULL
+ *   seed           scan orders of modes 2 and 3 for this instance (the batch
+ *                  ignores p->seed, so one batch can run a portfolio of seeds) */
 typedef struct {
     const int32_t *C;
     int64_t ldc;
@@ -226,6 +241,7 @@ typedef struct {
     int32_t *best_open_out;
     int32_t *assign_out;
     fs_trace_rec *trace_out;
+    uint64_t seed;
 } fs_instance;
 
 /* Tabu search (Section 4.3, Algorithm 3) of n independent instances of
@@ -295,8 +311,9 @@ fs_status fs_serve_register(fs_server *sv, const double *base_latlon_deg, int32_
 
 /* Submits a repositioning request: missions mission_ids[0..n) (host) of the
  * instance get the new coordinates new_pd_deg (host, n x 4 degrees), then the
- * instance is re-solved with p->tenure, p->iterations and p->mode (p->range_m
- * is ignored), warm-started from its previous best placement (base ranking
+ * instance is re-solved with p->tenure, p->iterations and p->mode, which is
+ * 0 or 1 (p->range_m and p->seed are ignored; modes 2 and 3 are FS_E_INVALID
+ * here), warm-started from its previous best placement (base ranking
  * for its first request).  n may be 0.  Thread-safe.
  * Errors: FS_E_NOTFOUND (instance), FS_E_INVALID (ids, params), FS_E_CLOSED,
  * FS_E_DEVICE after a device failure. */

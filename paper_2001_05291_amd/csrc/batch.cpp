@@ -54,6 +54,7 @@ extern "C" fs_status fs_tabu_solve_batch(const fs_instance *inst, int32_t n, con
         sp.T = p->tenure;
         sp.N = p->iterations;
         sp.mode = p->mode;
+        sp.seed = q.seed;
         sp.init_host = q.init_open ? inits[i].data() : nullptr;
         sp.trace = q.trace_out;
         sp.best_out = q.best_open_out;

@@ -69,7 +69,7 @@ fs_status check_params(const fs_params *p)
     if (p->iterations < 0) return fail(FS_E_INVALID, "iterations %d < 0", p->iterations);
     if ((int64_t)p->iterations + p->tenure >= INT32_MAX)
         return fail(FS_E_INVALID, "iterations + tenure overflow int32");
-    if (p->mode != 0 && p->mode != 1) return fail(FS_E_INVALID, "mode %d not 0 or 1", p->mode);
+    if (p->mode < 0 || p->mode > 3) return fail(FS_E_INVALID, "mode %d not in 0..3", p->mode);
     return FS_OK;
 }
 

@@ -23,6 +23,7 @@ struct InstDesc {
     const int32_t *C;
     int64_t ldc;
     int32_t B, M, Mp, K, R, T, N, mode;
+    uint64_t seed;           // permuted searches (modes 2, 3): seed of the scan orders
     int32_t nclosed, chunk, nsplit, ngroups;
     int32_t active;          // 0: every kernel skips this instance
     int32_t start_step;      // launch step at which this instance's iteration 0 ends

@@ -58,10 +58,15 @@ __device__ __forceinline__ bool better(int32_t ca, int64_t da, int32_t cb, int64
 }
 
 // Move order: coverage desc, distance asc, out-base asc, in-base asc.
+// The move order: permuted searches (KEYED) take the lowest priority (keys
+// are distinct within a pass); the other modes take coverage desc, distance
+// asc, out-base asc, in-base asc (their keys are all 0).
+template <bool KEYED>
 __device__ __forceinline__ bool cand_better(const Candidate &a, const Candidate &b)
 {
     if (!a.valid) return false;
     if (!b.valid) return true;
+    if (KEYED) return a.key < b.key;
     if (a.cov != b.cov) return a.cov > b.cov;
     if (a.dist != b.dist) return a.dist < b.dist;
     if (a.i_base != b.i_base) return a.i_base < b.i_base;
@@ -82,6 +87,7 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
     return v;
 }
 
+template <bool KEYED>
 __device__ __forceinline__ Candidate shfl_xor_cand(const Candidate &c, int off)
 {
     Candidate o;
@@ -92,27 +98,42 @@ __device__ __forceinline__ Candidate shfl_xor_cand(const Candidate &c, int off)
     o.i_slot = __shfl_xor(c.i_slot, off, 64);
     o.j_slot = __shfl_xor(c.j_slot, off, 64);
     o.dist = __shfl_xor(c.dist, off, 64);
+    o.key = KEYED ? __shfl_xor(c.key, off, 64) : c.key;
     return o;
 }
 
 // Best candidate of the wave under the move order (a total order, so the
 // result does not depend on the reduction order); the same in every lane.
+template <bool KEYED>
 __device__ __forceinline__ Candidate wave_best(Candidate c)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        const Candidate o = shfl_xor_cand(c, off);
-        if (cand_better(o, c)) c = o;
+        const Candidate o = shfl_xor_cand<KEYED>(c, off);
+        if (cand_better<KEYED>(o, c)) c = o;
     }
     return c;
 }
 
+// Scan orders of the permuted searches: the SplitMix64 output function
+// (Steele, Lea and Flood, OOPSLA 2014) over counters.  The priority of swap
+// (i out, j in) in pass p is mix64(z_p + (i B + j + 1) G) with
+// z_p = mix64(seed + (p + 1) G); for fixed z_p it is injective in (i, j).
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // Best candidate of the workgroup under the move order (a total order, so the
 // result does not depend on the reduction order); valid in every thread.
-template <int BS = kBlock>
+template <int BS, bool KEYED>
 __device__ Candidate block_best(Candidate c, Candidate *s_red /* BS/64 + 1 */)
 {
-    c = wave_best(c);
+    c = wave_best<KEYED>(c);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) s_red[wave] = c;
@@ -120,7 +141,7 @@ __device__ Candidate block_best(Candidate c, Candidate *s_red /* BS/64 + 1 */)
     if (threadIdx.x == 0) {
         Candidate b = s_red[0];
         for (int w = 1; w < BS / 64; ++w)
-            if (cand_better(s_red[w], b)) b = s_red[w];
+            if (cand_better<KEYED>(s_red[w], b)) b = s_red[w];
         s_red[BS / 64] = b;
     }
     __syncthreads();
@@ -440,14 +461,19 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         Candidate best{};
         for (int32_t q = threadIdx.x; q < ncand; q += kBlock) {
             const Candidate c = d.cand[q];
-            if (cand_better(c, best)) best = c;
+            if (d.mode >= 2 ? cand_better<true>(c, best) : cand_better<false>(c, best)) best = c;
         }
         const int32_t *cur_open = d.open;
         for (int k = threadIdx.x; k < K; k += kBlock) {
             s_open[k] = cur_open[k];
             if (TY) s_rot[k] = d.open_rot[k];
         }
-        best = block_best(best, s_red);   // barriers: s_open complete too
+        // barriers: s_open complete too
+        best = d.mode >= 2 ? block_best<kBlock, true>(best, s_red)
+                           : block_best<kBlock, false>(best, s_red);
+        // (permuted searches at the end of a pass keep going: every workgroup
+        // recomputes the unchanged placement's state, and the leader either
+        // starts the next pass or stops; nothing here reads what it writes)
         if (!best.valid && d.mode == 1) {
             // local optimum: stop; the placement and its state stay as they are
             if (leader && threadIdx.x == 0) {
@@ -469,6 +495,16 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                         s.best_dist = best.dist;
                         s.best_iter = t;
                         improved = 1;
+                    }
+                    s.have_last = 1;
+                    s.last_key = best.key;
+                } else if (d.mode >= 2) {
+                    if (s.have_last) {   // end of the order: the next pass
+                        s.pass += 1;
+                        s.have_last = 0;
+                        s.last_key = 0;
+                    } else {             // a whole pass without improvement
+                        s.stopped = 1;
                     }
                 }
                 *st = s;
@@ -772,6 +808,8 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
     const int64_t cur_d = st.cur_dist, best_d = st.best_dist;
     const int32_t Gc = L.Lc[0];
     const int64_t Gd = L.Ld[0];
+    const bool perm = d.mode >= 2;
+    const uint64_t zp = perm ? mix64(d.seed + (uint64_t)(st.pass + 1) * kGolden) : 0;
     Candidate mine{};
     for (int32_t idx = threadIdx.x; idx < J * K; idx += BS) {
         const int32_t r = idx / K, k = idx - r * K;
@@ -782,7 +820,8 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
         const bool rot = L.orot[k] != 0;
         if (!rot && s_jhel[r]) continue;
         const bool two = NC == 2 && rot;
-        const int32_t cov = Gc + L.Lc[1 + k] + t1c[NC * r] + (two ? t1c[NC * r + 1] : 0) + L.bc[idx];
+        const int32_t cov =
+            Gc + L.Lc[1 + k] + t1c[NC * r] + (two ? t1c[NC * r + 1] : 0) + L.bc[idx];
         const int64_t dist =
             Gd + L.Ld[1 + k] + t1d[NC * r] + (two ? t1d[NC * r + 1] : 0) + (int64_t)L.bd[idx];
         const int32_t i = L.open[k], j = s_jrow[r];
@@ -791,10 +830,18 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
             d.sc_dist[(int64_t)k * d.B + j] = dist;
         }
         bool adm;
-        if (d.mode == 1)
+        uint64_t key = 0;
+        if (perm) {
+            // strictly improving, after the pass's last accepted move, and
+            // (Tabu variant) touching no tabu base
+            key = mix64(zp + ((uint64_t)i * (uint64_t)d.B + (uint64_t)j + 1) * kGolden);
+            adm = better(cov, dist, cur_c, cur_d) && !(st.have_last && key <= st.last_key) &&
+                  (d.mode == 2 || (L.otabu[k] < t && s_jtabu[r] < t));
+        } else if (d.mode == 1) {
             adm = better(cov, dist, cur_c, cur_d);
-        else
+        } else {
             adm = (L.otabu[k] < t && s_jtabu[r] < t) || better(cov, dist, best_c, best_d);
+        }
         if (adm) {
             Candidate c;
             c.valid = 1;
@@ -804,13 +851,14 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
             c.j_base = j;
             c.i_slot = k;
             c.j_slot = js;
-            if (cand_better(c, mine)) mine = c;
+            c.key = key;
+            if (perm ? cand_better<true>(c, mine) : cand_better<false>(c, mine)) mine = c;
         }
     }
     if (one_wave) {
-        mine = wave_best(mine);
+        mine = perm ? wave_best<true>(mine) : wave_best<false>(mine);
     } else {
-        mine = block_best<BS>(mine, s_red);
+        mine = perm ? block_best<BS, true>(mine, s_red) : block_best<BS, false>(mine, s_red);
     }
     if (threadIdx.x == 0) d.cand[g] = mine;
 }
@@ -826,7 +874,8 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
     const v4i *o1v = reinterpret_cast<const v4i *>(d.o1);
     const v4i *rows[J];
 #pragma unroll
-    for (int r = 0; r < J; ++r) rows[r] = reinterpret_cast<const v4i *>(d.C + (int64_t)jrow[r] * d.ldc);
+    for (int r = 0; r < J; ++r)
+        rows[r] = reinterpret_cast<const v4i *>(d.C + (int64_t)jrow[r] * d.ldc);
     const int32_t qend = m1 >> 2;
     for (int32_t q0 = (m0 >> 2) + threadIdx.x; q0 < qend; q0 += U * BS) {
         v4i cv[U][J], vb1[U], vb2[U], vo1[U];

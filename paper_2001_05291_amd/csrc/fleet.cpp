@@ -126,6 +126,8 @@ extern "C" fs_status fs_fleet_solve(const int32_t *C, int64_t ldc, int32_t B, in
     const int32_t K = fleet->rotary + fleet->fixed;
     FS_TRY(check_problem(C, ldc, B, M, K, p->range_m));
     FS_TRY(check_params(p));
+    if (p->mode > 1)
+        return fail(FS_E_INVALID, "typed fleets run modes 0 and 1 (mode %d requested)", p->mode);
     if (!best_open_out || !best_rotary_out || !score_out)
         return fail(FS_E_INVALID, "NULL output pointer");
     hipStream_t s = (hipStream_t)stream;
@@ -138,6 +140,7 @@ extern "C" fs_status fs_fleet_solve(const int32_t *C, int64_t ldc, int32_t B, in
     sp.T = p->tenure;
     sp.N = p->iterations;
     sp.mode = p->mode;
+    sp.seed = p->seed;
     sp.init_host = init_open ? ids.data() : nullptr;   // NULL: typed ranking on the device
     sp.init_rot = init_open ? init_rotary : nullptr;
     sp.trace = trace_out;

@@ -85,13 +85,14 @@ struct Candidate {
     int32_t i_base, j_base;  // move: base i leaves, base j enters
     int32_t i_slot, j_slot;  // positions in the open / closed lists
     int64_t dist;
+    uint64_t key;            // permuted searches: the move's priority in the pass (else 0)
 };
-static_assert(sizeof(Candidate) == 32, "candidate layout");
+static_assert(sizeof(Candidate) == 40, "candidate layout");
 
 // Per-solve search state, resident in device memory.
 struct SolveState {
     int32_t stopped;    // local search reached a local optimum
-    int32_t pad0;
+    int32_t pass;       // permuted searches: the pass (scan order) in progress
     int32_t cur_cov;
     int32_t best_cov;
     int64_t cur_dist;
@@ -99,7 +100,8 @@ struct SolveState {
     int32_t best_iter;
     int32_t error;      // refreshed value disagreed with the executed move's score
     int32_t err_iter;
-    int32_t pad;
+    int32_t have_last;  // permuted searches: this pass has accepted a move ...
+    uint64_t last_key;  // ... whose priority was last_key
 };
 
 // Accumulator of the per-placement sums: slot 0 is G (the placement's value),

@@ -13,6 +13,7 @@ struct InstSpec {
     const int32_t *C = nullptr;
     int64_t ldc = 0;
     int32_t B = 0, M = 0, K = 0, R = 0, T = 0, N = 0, mode = 0;
+    uint64_t seed = 0;
     const int32_t *init_host = nullptr;  // K ids on the host, or NULL: rank on the device
     fs_trace_rec *trace = nullptr;
     int32_t *best_out = nullptr;

@@ -127,6 +127,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
         d.T = p.T;
         d.N = p.N;
         d.mode = p.mode;
+        d.seed = p.seed;
         d.active = 1;
         d.start_step = 0;
         d.trace = p.trace;
@@ -329,8 +330,10 @@ fs_status collect_results(LaunchSet &ls, std::vector<fs_score> &scores,
     FS_TRY(engine_outputs(ls.tabs, ls.cfg, ls.d_scores, ls.d_errors, s));
     scores.assign(n, fs_score{});
     errors.assign(n, 0);
-    FS_HIP(hipMemcpyAsync(scores.data(), ls.d_scores, sizeof(fs_score) * n, hipMemcpyDeviceToHost, s));
-    FS_HIP(hipMemcpyAsync(errors.data(), ls.d_errors, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(scores.data(), ls.d_scores, sizeof(fs_score) * n, hipMemcpyDeviceToHost,
+                          s));
+    FS_HIP(hipMemcpyAsync(errors.data(), ls.d_errors, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                          s));
     FS_HIP(hipStreamSynchronize(s));
     return FS_OK;
 }

@@ -361,6 +361,7 @@ fs_status Server::admit(Request *r, int i, bool &admitted)
     d.T = r->p.tenure;
     d.N = r->p.iterations;
     d.mode = r->p.mode;
+    d.seed = r->p.seed;
     d.active = 1;
     d.start_step = step;
     d.need_rank = rank ? 1 : 0;
@@ -794,6 +795,8 @@ extern "C" fs_status fs_serve_submit(fs_server *sv, int64_t instance_id,
     if (n < 0 || (n > 0 && (!mission_ids || !new_pd_deg)))
         return fail(FS_E_INVALID, "bad mission list");
     FS_TRY(check_params(p));
+    if (p->mode > 1)
+        return fail(FS_E_INVALID, "the server runs modes 0 and 1 (mode %d requested)", p->mode);
     Server &S = sv->impl;
     std::unique_ptr<Request> r(new Request);
     std::lock_guard<std::mutex> lk(S.mu);

@@ -94,6 +94,7 @@ extern "C" fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int
     sp.T = p->tenure;
     sp.N = p->iterations;
     sp.mode = p->mode;
+    sp.seed = p->seed;
     sp.init_host = init.data();
     sp.trace = trace_out;
     sp.best_out = best_open_out;

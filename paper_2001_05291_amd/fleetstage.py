@@ -35,7 +35,15 @@ class FleetstageError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("tenure", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("range_m", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("range_m", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+assert ctypes.sizeof(Params) == 24
+
+# search modes: Tabu (best admissible move, aspiration), steepest local search,
+# and the paper's permuted local search / permuted Tabu search
+MODE_TABU, MODE_LOCAL, MODE_PERM_LOCAL, MODE_PERM_TABU = 0, 1, 2, 3
 
 
 class Score(ctypes.Structure):
@@ -47,10 +55,11 @@ class Instance(ctypes.Structure):
     _fields_ = [("C", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("B", ctypes.c_int32),
                 ("M", ctypes.c_int32), ("K", ctypes.c_int32), ("range_m", ctypes.c_int32),
                 ("init_open", ctypes.c_void_p), ("best_open_out", ctypes.c_void_p),
-                ("assign_out", ctypes.c_void_p), ("trace_out", ctypes.c_void_p)]
+                ("assign_out", ctypes.c_void_p), ("trace_out", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64)]
 
 
-assert ctypes.sizeof(Instance) == 64
+assert ctypes.sizeof(Instance) == 72
 
 
 class ServeConfig(ctypes.Structure):
@@ -233,10 +242,10 @@ class SolveResult:
 
 def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int = 0,
                init_open=None, M: int | None = None, want_assign: bool = True,
-               want_trace: bool = True, stream=None) -> SolveResult:
+               want_trace: bool = True, stream=None, seed: int = 0) -> SolveResult:
     B, M, ldc = _table(C, M)
     dev = C.device
-    p = Params(int(tenure), int(iterations), int(range_m), int(mode))
+    p = Params(int(tenure), int(iterations), int(range_m), int(mode), int(seed) % 2**64)
     best = torch.empty(K, dtype=torch.int32, device=dev)
     assign = torch.empty(M, dtype=torch.int32, device=dev) if want_assign else None
     n = max(int(iterations), 0)
@@ -258,8 +267,9 @@ def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int 
 def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
                      want_assign: bool = True, want_trace: bool = True, stream=None):
     """Solves many instances in one launch set.  Each item is a dict with keys
-    C (device int32 table), K, range_m, and optionally M and init_open.
-    Returns one SolveResult per instance (identical to tabu_solve alone)."""
+    C (device int32 table), K, range_m, and optionally M, init_open and seed
+    (scan orders of modes 2 and 3).  Returns one SolveResult per instance
+    (identical to tabu_solve alone)."""
     n = len(instances)
     arr = (Instance * n)()
     keep = []
@@ -287,6 +297,7 @@ def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
         arr[i].best_open_out = best.data_ptr()
         arr[i].assign_out = assign.data_ptr() if assign is not None else None
         arr[i].trace_out = trace.data_ptr() if (trace is not None and nrec > 0) else None
+        arr[i].seed = int(it.get("seed", 0)) % 2**64
     p = Params(int(tenure), int(iterations), 0, int(mode))
     scores = (Score * n)()
     _check(lib().fs_tabu_solve_batch(arr, n, ctypes.byref(p), scores, _stream(stream)))
@@ -345,13 +356,13 @@ class FleetResult(SolveResult):
 def fleet_solve(C, K_r: int, K_f: int, heliport, rotary_only, range_m: int, tenure: int,
                 iterations: int, mode: int = 0, init_open=None, init_rotary=None,
                 M: int | None = None, want_assign: bool = True, want_trace: bool = True,
-                stream=None) -> FleetResult:
+                stream=None, seed: int = 0) -> FleetResult:
     """Typed Tabu / local search over vehicle relocations (heterogeneous fleet)."""
     B, M, ldc = _table(C, M)
     dev = C.device
     f, keep = _fleet(K_r, K_f, heliport, rotary_only, dev, B, M)
     K = int(K_r) + int(K_f)
-    p = Params(int(tenure), int(iterations), int(range_m), int(mode))
+    p = Params(int(tenure), int(iterations), int(range_m), int(mode), int(seed) % 2**64)
     best = torch.empty(K, dtype=torch.int32, device=dev)
     brot = torch.empty(K, dtype=torch.int32, device=dev)
     assign = torch.empty(M, dtype=torch.int32, device=dev) if want_assign else None
@@ -421,10 +432,10 @@ class Server:
         return int(iid.value)
 
     def submit(self, instance_id: int, mission_ids, new_pd, tenure: int, iterations: int,
-               mode: int = 0) -> int:
+               mode: int = 0, seed: int = 0) -> int:
         ids = np.ascontiguousarray(mission_ids, dtype=np.int32)
         pd = np.ascontiguousarray(new_pd, dtype=np.float64).reshape(-1, 4)
-        p = Params(int(tenure), int(iterations), 0, int(mode))
+        p = Params(int(tenure), int(iterations), 0, int(mode), int(seed) % 2**64)
         t = ctypes.c_uint64()
         _check(lib().fs_serve_submit(self._h, int(instance_id), ids.ctypes.data if ids.size else None,
                                      pd.ctypes.data if ids.size else None, int(ids.size),
