@@ -18,6 +18,10 @@ scores K*(B-K) swap moves over M missions.  It is reported for the whole step
   portfolio     the paper's permuted local and Tabu searches (random scan
                 orders), ten seeds each in one batch launch: runs/s and the
                 upper / lower / average result;
+  optimum       a synthetic analogue of the paper's Table 1 and Fig. 2:
+                eleven small datasets against their exact optimum by GPU
+                enumeration (base ranking, random starts, ten-seed local and
+                Tabu searches: upper / lower / average gap);
   batch         the ragged batch (1,024 instances of uneven size, 200
                 iterations each): solves/s of one launch set against one solve
                 per instance, results identical;
@@ -71,6 +75,8 @@ def main():
     ap.add_argument("--serve-pool", default="1024,64",
                     help="resident instances of the repositioning load: small,large")
     ap.add_argument("--serve-slots", type=int, default=128)
+    ap.add_argument("--no-optimum", action="store_true",
+                    help="skip the exact-optimum leg (synthetic analogue of the paper's Table 1)")
     ap.add_argument("--no-portfolio", action="store_true",
                     help="skip the seed-portfolio leg (permuted local and Tabu searches)")
     ap.add_argument("--no-fleet", action="store_true",
@@ -171,6 +177,11 @@ def main():
         from paper_2001_05291_amd import portfoliobench
         portfolio = portfoliobench.run(fs, torch, workload=args.workload, log=log)
 
+    optimum = None
+    if not args.no_optimum:
+        from paper_2001_05291_amd import optimumbench
+        optimum = optimumbench.run(fs, torch, log=log)
+
     batch = None
     if not args.no_batch:
         from paper_2001_05291_amd import batchbench
@@ -206,6 +217,7 @@ def main():
         "cpu_baseline": cpu,
         "fleet": fleet,
         "portfolio": portfolio,
+        "optimum": optimum,
         "batch": batch,
         "serve": serve,
         "detail": {"sweep_ms_per_launch": sweep_ms / max(sweep_n, 1),

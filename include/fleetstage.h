@@ -175,6 +175,20 @@ fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int
                         int32_t *best_open_out, fs_score *score_out,
                         int32_t *assign_out, fs_trace_rec *trace_out, void *stream);
 
+/* Exact optimum of a small instance by enumeration: the stand-in for the
+ * exact solver the paper's evaluation compares against (Section 5, Table 1).
+ * Every K-subset of the B bases is scored (nearest open base per mission,
+ * coverage within range_m, the (coverage desc, distance asc) order of
+ * fs_tabu_solve); among equal values the first subset in lexicographic order
+ * of ascending ids wins.  best_open_out (device, K): the optimum, ascending;
+ * score_out (host): its value (best_iter 0); placements_out (host, or NULL):
+ * C(B, K).  The table is staged in on-chip memory: FS_E_INVALID when
+ * 8 (B + 1)(K + 1) + 4 B M exceeds 56 KiB, K > 16 or C(B, K) > 2^40, and for
+ * the checks of fs_tabu_solve. */
+fs_status fs_brute_optimum(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K,
+                           int32_t range_m, int32_t *best_open_out, fs_score *score_out,
+                           int64_t *placements_out, void *stream);
+
 /* ---------------------------------------------------------------- heterogeneous fleet
  *
  * The paper's full model (Section 3, Eq. 4-10): K_r rotary-wing and K_f

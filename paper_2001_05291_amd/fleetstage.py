@@ -105,6 +105,9 @@ def lib():
     L.fs_tabu_solve.restype = i32
     L.fs_tabu_solve.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(Params), vp, vp,
                                 ctypes.POINTER(Score), vp, vp, vp]
+    L.fs_brute_optimum.restype = i32
+    L.fs_brute_optimum.argtypes = [vp, i64, i32, i32, i32, i32, vp, ctypes.POINTER(Score),
+                                   ctypes.POINTER(i64), vp]
     L.fs_fleet_move_scores.restype = i32
     L.fs_fleet_move_scores.argtypes = [vp, i64, i32, i32, ctypes.POINTER(Fleet), vp, vp, i32,
                                        vp, vp, vp]
@@ -309,6 +312,18 @@ def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
         res.append(SolveResult(best, int(scores[i].coverage), int(scores[i].distance),
                                int(scores[i].best_iter), assign, tr))
     return res
+
+
+def brute_optimum(C, K: int, range_m: int, M: int | None = None, stream=None):
+    """Exact optimum by enumeration of all K-subsets (small instances):
+    (best_open device int32 K ascending, coverage, distance, placements)."""
+    B, M, ldc = _table(C, M)
+    best = torch.empty(int(K), dtype=torch.int32, device=C.device)
+    sc = Score()
+    n = ctypes.c_int64()
+    _check(lib().fs_brute_optimum(_table_ptr(C), ldc, B, M, int(K), int(range_m), _ptr(best),
+                                  ctypes.byref(sc), ctypes.byref(n), _stream(stream)))
+    return best, int(sc.coverage), int(sc.distance), int(n.value)
 
 
 # ---------------------------------------------------------------- heterogeneous fleet
