@@ -57,6 +57,9 @@ fs_status check_problem(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int
     FS_TRY(check_table(C, ldc, B, M));
     if (K < 1 || K > B) return fail(FS_E_INVALID, "K=%d must be in [1, B=%d]", K, B);
     if (K > kMaxK) return fail(FS_E_INVALID, "K=%d exceeds the supported %d vehicles", K, kMaxK);
+    if (B - K >= kMaxClosed)
+        return fail(FS_E_INVALID, "B - K = %d closed bases exceed the supported %d", B - K,
+                    kMaxClosed - 1);
     if (R < 0 || R == INT32_MAX) return fail(FS_E_INVALID, "range %d outside [0, INT32_MAX)", R);
     if ((int64_t)M + 3 > INT32_MAX) return fail(FS_E_INVALID, "M=%d too large", M);
     return FS_OK;

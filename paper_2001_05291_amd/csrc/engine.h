@@ -115,6 +115,10 @@ struct EngineTables {
     int nscore = 0;
     const Tile *refresh = nullptr;
     int nrefresh = 0;
+    // one instance with the tiles of build_tiles (row group major, mission
+    // chunk minor): the sweep, score and refresh kernels take their tile from
+    // the block index instead of reading the table
+    bool single = false;
 };
 
 // Geometry of one instance for a given J (rows per workgroup).

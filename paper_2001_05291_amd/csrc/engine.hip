@@ -61,11 +61,31 @@ __device__ __forceinline__ bool better(int32_t ca, int64_t da, int32_t cb, int64
 // The move order: permuted searches (KEYED) take the lowest priority (keys
 // are distinct within a pass); the other modes take coverage desc, distance
 // asc, out-base asc, in-base asc (their keys are all 0).
+__device__ __forceinline__ Candidate no_cand()
+{
+    Candidate c;
+    c.cov = -1;
+    c.i_base = c.j_base = 0;
+    c.slots = 0;
+    c.dist = 0;
+    c.key = 0;
+    return c;
+}
+__device__ __forceinline__ bool cand_valid(const Candidate &c) { return c.cov >= 0; }
+__device__ __forceinline__ int32_t cand_i_slot(const Candidate &c)
+{
+    return (int32_t)(c.slots & ((1u << kSlotBits) - 1));
+}
+__device__ __forceinline__ int32_t cand_j_slot(const Candidate &c)
+{
+    return (int32_t)(c.slots >> kSlotBits);
+}
+
 template <bool KEYED>
 __device__ __forceinline__ bool cand_better(const Candidate &a, const Candidate &b)
 {
-    if (!a.valid) return false;
-    if (!b.valid) return true;
+    if (!cand_valid(a)) return false;
+    if (!cand_valid(b)) return true;
     if (KEYED) return a.key < b.key;
     if (a.cov != b.cov) return a.cov > b.cov;
     if (a.dist != b.dist) return a.dist < b.dist;
@@ -91,12 +111,10 @@ template <bool KEYED>
 __device__ __forceinline__ Candidate shfl_xor_cand(const Candidate &c, int off)
 {
     Candidate o;
-    o.valid = __shfl_xor(c.valid, off, 64);
     o.cov = __shfl_xor(c.cov, off, 64);
     o.i_base = __shfl_xor(c.i_base, off, 64);
     o.j_base = __shfl_xor(c.j_base, off, 64);
-    o.i_slot = __shfl_xor(c.i_slot, off, 64);
-    o.j_slot = __shfl_xor(c.j_slot, off, 64);
+    o.slots = (uint32_t)__shfl_xor((int32_t)c.slots, off, 64);
     o.dist = __shfl_xor(c.dist, off, 64);
     o.key = KEYED ? __shfl_xor(c.key, off, 64) : c.key;
     return o;
@@ -126,6 +144,23 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+// The workgroup's tile: from the table, or (tiles == NULL: one instance,
+// tiles row group major and mission chunk minor) from the block index, so
+// that the descriptor load does not wait for a tile load.
+__device__ __forceinline__ Tile sweep_tile(const InstDesc *descs, const Tile *tiles)
+{
+    if (tiles) return tiles[blockIdx.x];
+    const int32_t ns = descs[0].nsplit;
+    const int32_t g = (int32_t)blockIdx.x / ns;
+    return Tile{0, g, (int32_t)blockIdx.x - g * ns, 0};
+}
+
+__device__ __forceinline__ Tile group_tile(const Tile *tiles)
+{
+    if (tiles) return tiles[blockIdx.x];
+    return Tile{0, (int32_t)blockIdx.x, 0, 0};
 }
 
 // Best candidate of the workgroup under the move order (a total order, so the
@@ -432,7 +467,7 @@ template <int MPT, bool TY>
 __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__ descs,
                                                     const Tile *__restrict__ tiles, int32_t step)
 {
-    const Tile tl = tiles[blockIdx.x];
+    const Tile tl = group_tile(tiles);
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
@@ -457,8 +492,9 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             if (leader && threadIdx.x == 0) write_record(d, t, *st, 0, -1, -1);
             return;
         }
-        const int32_t ncand = d.ngroups > 0 ? d.ngroups : 1;
-        Candidate best{};
+        // (no closed base: no row group and no move)
+        const int32_t ncand = d.ngroups;
+        Candidate best = no_cand();
         for (int32_t q = threadIdx.x; q < ncand; q += kBlock) {
             const Candidate c = d.cand[q];
             if (d.mode >= 2 ? cand_better<true>(c, best) : cand_better<false>(c, best)) best = c;
@@ -474,7 +510,9 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         // (permuted searches at the end of a pass keep going: every workgroup
         // recomputes the unchanged placement's state, and the leader either
         // starts the next pass or stops; nothing here reads what it writes)
-        if (!best.valid && d.mode == 1) {
+        const bool valid = cand_valid(best);
+        const int32_t i_slot = cand_i_slot(best), j_slot = cand_j_slot(best);
+        if (!valid && d.mode == 1) {
             // local optimum: stop; the placement and its state stay as they are
             if (leader && threadIdx.x == 0) {
                 st->stopped = 1;
@@ -487,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             if (threadIdx.x == 0) {
                 SolveState s = *st;
                 int32_t improved = 0;
-                if (best.valid) {
+                if (valid) {
                     s.cur_cov = best.cov;
                     s.cur_dist = best.dist;
                     if (better(best.cov, best.dist, s.best_cov, s.best_dist)) {
@@ -508,29 +546,29 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                     }
                 }
                 *st = s;
-                write_record(d, t, s, best.valid, best.i_base, best.j_base);
+                write_record(d, t, s, valid, best.i_base, best.j_base);
                 s_improved = improved;
             }
             __syncthreads();
             // the swap: the two bases trade list slots, and both stay tabu
             // through iteration t + T (the expiry travels with the base)
-            if (best.valid && threadIdx.x == 0) {
-                d.open[best.i_slot] = best.j_base;
-                d.open_tabu[best.i_slot] = t + d.T;
-                d.closed[best.j_slot] = best.i_base;
-                d.closed_tabu[best.j_slot] = t + d.T;
+            if (valid && threadIdx.x == 0) {
+                d.open[i_slot] = best.j_base;
+                d.open_tabu[i_slot] = t + d.T;
+                d.closed[j_slot] = best.i_base;
+                d.closed_tabu[j_slot] = t + d.T;
                 if (TY && d.typed) {   // the base kinds trade list slots with the bases
-                    const int32_t h = d.open_hel[best.i_slot];
-                    d.open_hel[best.i_slot] = d.closed_hel[best.j_slot];
-                    d.closed_hel[best.j_slot] = h;
+                    const int32_t h = d.open_hel[i_slot];
+                    d.open_hel[i_slot] = d.closed_hel[j_slot];
+                    d.closed_hel[j_slot] = h;
                 }
             }
             if (s_improved)
                 for (int k = threadIdx.x; k < K; k += kBlock)
-                    d.best_open[k] = (best.valid && k == best.i_slot) ? best.j_base : s_open[k];
+                    d.best_open[k] = (valid && k == i_slot) ? best.j_base : s_open[k];
         }
         __syncthreads();
-        if (best.valid && threadIdx.x == 0) s_open[best.i_slot] = best.j_base;
+        if (valid && threadIdx.x == 0) s_open[i_slot] = best.j_base;
     } else {
         const int32_t *first = d.open;
         for (int k = threadIdx.x; k < K; k += kBlock) {
@@ -810,7 +848,7 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
     const int64_t Gd = L.Ld[0];
     const bool perm = d.mode >= 2;
     const uint64_t zp = perm ? mix64(d.seed + (uint64_t)(st.pass + 1) * kGolden) : 0;
-    Candidate mine{};
+    Candidate mine = no_cand();
     for (int32_t idx = threadIdx.x; idx < J * K; idx += BS) {
         const int32_t r = idx / K, k = idx - r * K;
         const int32_t js = g * J + r;
@@ -844,13 +882,11 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
         }
         if (adm) {
             Candidate c;
-            c.valid = 1;
             c.cov = cov;
             c.dist = dist;
             c.i_base = i;
             c.j_base = j;
-            c.i_slot = k;
-            c.j_slot = js;
+            c.slots = (uint32_t)k | ((uint32_t)js << kSlotBits);
             c.key = key;
             if (perm ? cand_better<true>(c, mine) : cand_better<false>(c, mine)) mine = c;
         }
@@ -1234,7 +1270,7 @@ template <int BS, int J, int U, bool VEC4, bool NT, bool Q, int NC>
 __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs,
                                                   const Tile *__restrict__ tiles, int32_t step)
 {
-    const Tile tl = tiles[blockIdx.x];
+    const Tile tl = sweep_tile(descs, tiles);
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
@@ -1322,7 +1358,7 @@ template <int J>
 __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ descs,
                                                   const Tile *__restrict__ tiles, int32_t step)
 {
-    const Tile tl = tiles[blockIdx.x];
+    const Tile tl = group_tile(tiles);
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
@@ -1469,19 +1505,21 @@ fs_status launch_sweep_t(const EngineTables &t, const EngineConfig &c, int32_t s
             if (c.wide) {
                 launch_timed(k_sweep<kWideBlock, J, U, VEC4, NT, Q, NC>, dim3(t.nsweep),
                              dim3(kWideBlock), lds, s, tm.start(), score ? nullptr : tm.stop(),
-                             t.desc, t.sweep, step);
+                             t.desc, t.single ? nullptr : t.sweep, step);
                 launched = true;
             }
         }
         if (!launched)
             launch_timed(k_sweep<kBlock, J, U, VEC4, NT, Q, NC>, dim3(t.nsweep), dim3(kBlock), lds,
-                         s, tm.start(), score ? nullptr : tm.stop(), t.desc, t.sweep, step);
+                         s, tm.start(), score ? nullptr : tm.stop(), t.desc,
+                         t.single ? nullptr : t.sweep, step);
         FS_HIP(hipGetLastError());
         if (!score) tm.used();
     }
     if (score) {
         launch_timed(k_score<J>, dim3(t.nscore), dim3(kBlock), lds, s,
-                     t.nsweep > 0 ? nullptr : tm.start(), tm.stop(), t.desc, t.score, step);
+                     t.nsweep > 0 ? nullptr : tm.start(), tm.stop(), t.desc,
+                     t.single ? nullptr : t.score, step);
         FS_HIP(hipGetLastError());
         tm.used();
     }
@@ -1715,8 +1753,8 @@ RefreshKernel refresh_kernel(const EngineConfig &c)
 fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s)
 {
     if (t.nrefresh > 0) {
-        refresh_kernel(c)<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(t.desc, t.refresh,
-                                                                               step0);
+        refresh_kernel(c)<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(
+            t.desc, t.single ? nullptr : t.refresh, step0);
         FS_HIP(hipGetLastError());
     }
     k_init_score<<<t.ninst, kBlock, 0, s>>>(t.desc);
@@ -1749,6 +1787,7 @@ fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t ste
         tall.nsweep = t.nsweep_tall;
         tall.score = nullptr;
         tall.nscore = 0;
+        tall.single = false;   // its own tile table
         EngineConfig ct = c;
         ct.J = c.J_tall;
         ct.U = c.U_tall;
@@ -1765,7 +1804,7 @@ fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t s
     TimedLaunch timed(1);
     launch_timed(refresh_kernel(c), dim3(t.nrefresh), dim3(kBlock),
                  (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), t.desc,
-                 t.refresh, step);
+                 t.single ? nullptr : t.refresh, step);
     FS_HIP(hipGetLastError());
     timed.used();
     return FS_OK;

@@ -80,14 +80,16 @@ struct Score {
 
 // Best admissible move found by one sweep workgroup (or none: valid == 0).
 struct Candidate {
-    int32_t valid;
-    int32_t cov;
+    int32_t cov;             // covered missions of the moved placement; -1: no move
     int32_t i_base, j_base;  // move: base i leaves, base j enters
-    int32_t i_slot, j_slot;  // positions in the open / closed lists
+    uint32_t slots;          // position of i in the open list (low kSlotBits bits) and
+                             // of j in the closed list (the rest)
     int64_t dist;
     uint64_t key;            // permuted searches: the move's priority in the pass (else 0)
 };
-static_assert(sizeof(Candidate) == 40, "candidate layout");
+static_assert(sizeof(Candidate) == 32, "candidate layout");
+constexpr int kSlotBits = 10;                       // open slots: K <= kMaxK = 1 << 10
+constexpr int32_t kMaxClosed = 1 << (32 - kSlotBits);   // closed slots per instance
 
 // Per-solve search state, resident in device memory.
 struct SolveState {

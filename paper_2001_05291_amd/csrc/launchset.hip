@@ -181,6 +181,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     t.nscore = (int)score.size();
     t.refresh = (const Tile *)(base + o_refresh);
     t.nrefresh = (int)refresh.size();
+    t.single = n == 1;
     ls.rank_rows = (const Tile *)(base + o_rank);
     ls.nrank_rows = (int)rank_rows.size();
     ls.d_scores = (fs_score *)(base + o_scores);
