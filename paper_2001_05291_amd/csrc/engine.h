@@ -24,6 +24,14 @@ struct InstDesc {
     int64_t ldc;
     int32_t B, M, Mp, K, R, T, N, mode;
     uint64_t seed;           // permuted searches (modes 2, 3): seed of the scan orders
+    // sparse sweep (one instance, homogeneous, K <= kSparseW): row groups are
+    // blocks of kSparseW base ids (ngroups = blocks, nsplit = mission chunks);
+    // lst_cost / lst_id hold, for each block and mission, the block's bases in
+    // ascending (cost, id) order, rank-major: [block][rank][Mp]
+    int32_t sparse;
+    int32_t *lst_cost;
+    unsigned char *lst_id;
+    int32_t *base_slot;      // B: closed slot (>= 0) or -1 - open slot
     int32_t nclosed, chunk, nsplit, ngroups;
     int32_t active;          // 0: every kernel skips this instance
     int32_t start_step;      // launch step at which this instance's iteration 0 ends
@@ -76,7 +84,13 @@ struct Tile {
 // Per-instance launch geometry chosen on the host.
 struct InstPlan {
     int32_t nclosed, ngroups, nsplit, chunk;
+    int32_t sparse = 0;      // row groups are base blocks of the sparse sweep
 };
+
+constexpr int kSparseW = 64;   // bases per block of the sparse sweep (one wave)
+constexpr int kSparseMaxK = 64;
+// Plan of the sparse sweep: blocks of kSparseW bases x mission chunks.
+InstPlan plan_sparse(int32_t B, int32_t M, int32_t K, int target_wg);
 
 // Engine configuration shared by all instances of one launch set.
 struct EngineConfig {
@@ -95,6 +109,7 @@ struct EngineConfig {
     // for small K and many missions); the refresh tiles are built to match
     int refresh_mpt = kRefreshMissions;
     int Kmax = 1;
+    bool sparse = false;   // the sparse sweep (single homogeneous instance)
     // some instance has a typed fleet: the sweep keeps the rotary-only
     // missions' common term apart (queued or scalar variant, U = 1, 256
     // threads; other launch sets never pay for it)
@@ -153,6 +168,8 @@ fs_status engine_fleet_lists(const EngineTables &t, hipStream_t s);
 // State of the initial placement, then cur = best = its value.  step0 is the
 // launch step at which the instances' iteration 0 ends (their start_step).
 fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s);
+// Sparse sweep: the sorted lists and the base -> slot map (after engine_init).
+fs_status engine_sparse_prepare(const EngineTables &t, hipStream_t s);
 // Scores every swap of every instance and keeps each row group's best
 // admissible move.
 fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step,

@@ -557,6 +557,10 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                 d.open_tabu[i_slot] = t + d.T;
                 d.closed[j_slot] = best.i_base;
                 d.closed_tabu[j_slot] = t + d.T;
+                if (d.sparse) {
+                    d.base_slot[best.j_base] = -1 - i_slot;
+                    d.base_slot[best.i_base] = j_slot;
+                }
                 if (TY && d.typed) {   // the base kinds trade list slots with the bases
                     const int32_t h = d.open_hel[i_slot];
                     d.open_hel[i_slot] = d.closed_hel[j_slot];
@@ -837,7 +841,7 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
                             int32_t g,
                             const int32_t *s_jrow, const int32_t *s_jtabu, const int32_t *s_jhel,
                             const SweepLds &L, const int32_t *t1c, const int64_t *t1d,
-                            Candidate *s_red)
+                            Candidate *s_red, const int32_t *s_jslot = nullptr)
 {
     const int32_t K = d.K;
     const bool one_wave = J * K <= 64;
@@ -851,8 +855,9 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
     Candidate mine = no_cand();
     for (int32_t idx = threadIdx.x; idx < J * K; idx += BS) {
         const int32_t r = idx / K, k = idx - r * K;
-        const int32_t js = g * J + r;
-        if (js >= d.nclosed) continue;
+        // rows are consecutive closed slots, or (sparse sweep) listed in s_jslot
+        const int32_t js = s_jslot ? s_jslot[r] : g * J + r;
+        if (!s_jslot && js >= d.nclosed) continue;
         // moving a fixed-wing vehicle changes nothing for rotary-only missions,
         // and cannot land on a heliport
         const bool rot = L.orot[k] != 0;
@@ -1353,6 +1358,273 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     }
 }
 
+// ---------------------------------------------------------------- sparse sweep (A3)
+//
+// Only elements with c < b2 contribute to a move score.  For each block of
+// kSparseW consecutive base ids and each mission, the block's bases are kept
+// sorted by (cost, id); a sweep then walks each mission's sorted list only
+// while the cost is below b2, so it touches the contributing elements (and one
+// more per list) instead of every closed row.  The terms added are exactly the
+// dense sweep's (the same integer arithmetic on the same elements), so the
+// scores are identical.
+
+// Sorted lists of one block x 64 missions: the C tile is staged in LDS, each
+// wave sorts a mission's 64 (cost, local id) keys across its lanes (bitonic,
+// ascending; the sign bit is flipped so that the unsigned key order is the
+// signed cost order), and the sorted columns go out rank-major.  Bases past B
+// and missions past M sort last with cost INT32_MAX, which no b2 exceeds.
+__global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restrict__ descs)
+{
+    const InstDesc &d = descs[0];
+    const int32_t nmg = (d.Mp + 63) / 64;
+    const int32_t q = (int32_t)blockIdx.x / nmg, mg = (int32_t)blockIdx.x - q * nmg;
+    __shared__ int32_t s_c[kSparseW][65];
+    __shared__ int32_t s_cost[kSparseW][64];
+    __shared__ unsigned char s_id[kSparseW][64];
+    for (int32_t idx = threadIdx.x; idx < kSparseW * 64; idx += kBlock) {
+        const int32_t l = idx >> 6, mm = idx & 63;
+        const int32_t b = q * kSparseW + l, m = mg * 64 + mm;
+        s_c[l][mm] = (b < d.B && m < d.M) ? d.C[(int64_t)b * d.ldc + m] : INT32_MAX;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = 0; i < 64 / (kBlock / 64); ++i) {
+        const int32_t mm = wave * (64 / (kBlock / 64)) + i;
+        uint64_t key = ((uint64_t)((uint32_t)s_c[lane][mm] ^ 0x80000000u) << 6) | (uint64_t)lane;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const uint64_t other = __shfl_xor(key, j, 64);
+                const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+                key = (lower == up) ? min(key, other) : max(key, other);
+            }
+        }
+        s_cost[lane][mm] = (int32_t)((uint32_t)(key >> 6) ^ 0x80000000u);
+        s_id[lane][mm] = (unsigned char)(key & 63);
+    }
+    __syncthreads();
+    for (int32_t idx = threadIdx.x; idx < kSparseW * 64; idx += kBlock) {
+        const int32_t r = idx >> 6, mm = idx & 63, m = mg * 64 + mm;
+        if (m < d.Mp) {
+            const int64_t at = ((int64_t)q * kSparseW + r) * d.Mp + m;
+            d.lst_cost[at] = s_cost[r][mm];
+            d.lst_id[at] = s_id[r][mm];
+        }
+    }
+}
+
+// base_slot from the open and closed lists (before the first sparse sweep).
+__global__ __launch_bounds__(kBlock) void k_sparse_slots(const InstDesc *__restrict__ descs)
+{
+    const InstDesc &d = descs[0];
+    for (int32_t js = threadIdx.x + blockIdx.x * kBlock; js < d.nclosed; js += gridDim.x * kBlock)
+        d.base_slot[d.closed[js]] = js;
+    for (int32_t k = threadIdx.x + blockIdx.x * kBlock; k < d.K; k += gridDim.x * kBlock)
+        d.base_slot[d.open[k]] = -1 - k;
+}
+
+// The dense visit's terms for one element c < b2 of a row, added to the
+// row's common term and bin in LDS.
+__device__ __forceinline__ void visit_sparse(int32_t c, int32_t b1, int32_t b2, int32_t o1,
+                                             int32_t g1c, int32_t g1d, int32_t g2c, int32_t g2d,
+                                             int32_t R, int32_t *t1c, u64 *t1d,
+                                             int32_t *__restrict__ bc, u64 *__restrict__ bd)
+{
+    const int32_t v1 = min(c, b1);
+    const int32_t u = max(c, b1);
+    const int32_t cv = v1 <= R;
+    const int32_t tc = cv - g1c;
+    const int32_t td = (cv ? v1 : 0) - g1d;
+    if (tc | td) {
+        atomicAdd(t1c, tc);
+        atomicAdd(t1d, (u64)(int64_t)td);
+    }
+    const int32_t cu = u <= R;
+    const int32_t dc = cu - g2c;
+    const int32_t dd = (cu ? u : 0) - g2d;
+    const int32_t slot = o1 & 0xFFFF;
+    if (dc | dd) {
+        atomicAdd(bc + slot, dc);
+        atomicAdd(bd + slot, (u64)(int64_t)dd);
+    }
+}
+
+// The closed bases of block q as rows (ascending id): s_jrow / s_jslot /
+// s_jtabu, and s_rowof[local id] = row or -1.  Called by the first wave.
+__device__ __forceinline__ void sparse_rows(const InstDesc &d, int32_t q, bool with_tabu,
+                                            int32_t *s_jrow, int32_t *s_jslot, int32_t *s_jtabu,
+                                            int32_t *s_jhel, int32_t *s_rowof, int32_t *s_nrows)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t b = q * kSparseW + lane;
+    const int32_t slot = b < d.B ? d.base_slot[b] : -1;
+    const bool closed = slot >= 0;
+    const u64 mask = __builtin_amdgcn_ballot_w64(closed);
+    const int32_t row = (int32_t)__builtin_popcountll(mask & ((1ull << lane) - 1));
+    s_rowof[lane] = closed ? row : -1;
+    if (closed) {
+        s_jrow[row] = b;
+        s_jslot[row] = slot;
+        s_jtabu[row] = with_tabu ? d.closed_tabu[slot] : 0;
+        s_jhel[row] = 0;
+    }
+    if (lane == 0) *s_nrows = (int32_t)__builtin_popcountll(mask);
+}
+
+constexpr int kSparseRanks = 8;   // ranks loaded together per step of a walk
+
+// One workgroup = base block g x mission chunk sp.  Each wave takes 64
+// missions at a time and walks their lists kSparseRanks ranks per step while
+// any lane still has c < b2.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sweep_sparse(const InstDesc *__restrict__ descs,
+                                                     const Tile *__restrict__ tiles, int32_t step)
+{
+    const Tile tl = sweep_tile(descs, tiles);
+    const InstDesc &d = descs[tl.inst];
+    if (!d.active) return;
+    const int32_t t = step - d.start_step;
+    if (t < 1 || t > d.N) return;
+    const SolveState st = *d.st;
+    if (st.stopped) return;
+    const bool scoring = d.nsplit == 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t K = d.K, R = d.R;
+    const SweepLds L = carve_lds(smem, kSparseW, K);
+    __shared__ int32_t s_jrow[kSparseW], s_jslot[kSparseW], s_jtabu[kSparseW],
+        s_jhel[kSparseW], s_rowof[kSparseW];
+    __shared__ int32_t s_t1c[kSparseW];
+    __shared__ u64 s_t1d[kSparseW];
+    __shared__ int32_t s_nrows;
+    __shared__ Candidate s_red[BS / 64 + 1];
+
+    if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
+    for (int q = threadIdx.x; q < kSparseW * K; q += BS) {
+        L.bd[q] = 0;
+        L.bc[q] = 0;
+    }
+    if (threadIdx.x < kSparseW) {
+        s_t1c[threadIdx.x] = 0;
+        s_t1d[threadIdx.x] = 0;
+        sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
+    }
+    if (scoring) load_slot_inputs(d, t, L, false);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int32_t m0 = tl.sp * d.chunk, m1 = min(d.Mp, m0 + d.chunk);
+    const int64_t Mp = d.Mp;
+    const int32_t *lc = d.lst_cost + (int64_t)tl.g * kSparseW * Mp;
+    const unsigned char *li = d.lst_id + (int64_t)tl.g * kSparseW * Mp;
+    for (int32_t mw = m0 + (int32_t)(threadIdx.x & ~63); mw < m1; mw += BS) {
+        const int32_t m = mw + lane;
+        const bool in = m < m1;
+        const int32_t b1 = in ? d.b1[m] : 0, b2 = in ? d.b2[m] : INT32_MIN,
+                      o1 = in ? d.o1[m] : 0;
+        const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
+        const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+        const int32_t mc = in ? m : m0;   // in-bounds address for idle lanes
+        // ranks in batches of kSparseRanks, every load of a batch in flight
+        // together; the wave stops at the first batch where no lane is below b2
+        bool act = in;
+        for (int32_t r0 = 0; r0 < kSparseW; r0 += kSparseRanks) {
+            if (__builtin_amdgcn_ballot_w64(act) == 0) break;
+            int32_t cs[kSparseRanks];
+            int32_t ids[kSparseRanks];
+#pragma unroll
+            for (int r = 0; r < kSparseRanks; ++r) {
+                cs[r] = lc[(r0 + r) * Mp + mc];
+                ids[r] = li[(r0 + r) * Mp + mc];
+            }
+#pragma unroll
+            for (int r = 0; r < kSparseRanks; ++r) {
+                if (act && cs[r] < b2) {
+                    const int32_t row = s_rowof[ids[r]];
+                    if (row >= 0)
+                        visit_sparse(cs[r], b1, b2, o1, g1c, g1d, g2c, g2d, R, s_t1c + row,
+                                     s_t1d + row, L.bc + row * K, L.bd + row * K);
+                } else {
+                    act = false;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int32_t nrows = s_nrows;
+    if (scoring) {
+        __shared__ int64_t s_t1ds[kSparseW];
+        if (threadIdx.x < kSparseW) s_t1ds[threadIdx.x] = (int64_t)s_t1d[threadIdx.x];
+        __syncthreads();
+        score_group<BS>(d, st, nrows, 1, t, tl.g, s_jrow, s_jtabu, s_jhel, L, s_t1c, s_t1ds,
+                            s_red, s_jslot);
+    } else {
+        // this chunk's [T1, bin_0 .. bin_{K-1}] per row, added into the
+        // block's sums (nonzero entries only; integer atomics, exact in any
+        // order); k_score_sparse scores the block after every chunk
+        const int32_t K1 = K + 1;
+        const int64_t base = (int64_t)tl.g * kSparseW * K1;
+        unsigned int *pc = reinterpret_cast<unsigned int *>(d.part_cov) + base;
+        u64 *pd = reinterpret_cast<u64 *>(d.part_dist) + base;
+        for (int32_t idx = threadIdx.x; idx < nrows * K1; idx += BS) {
+            const int32_t r = idx / K1, k = idx - r * K1;
+            const int32_t c = k == 0 ? s_t1c[r] : L.bc[r * K + k - 1];
+            const u64 dd = k == 0 ? s_t1d[r] : L.bd[r * K + k - 1];
+            if (c) atomicAdd(pc + idx, (unsigned int)c);
+            if (dd) atomicAdd(pd + idx, dd);
+        }
+    }
+}
+
+// Scores one base block from its sums over the mission chunks (added by the
+// sweep's chunks) and clears them for the next iteration (all kSparseW rows:
+// the next iteration's rows may differ).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_score_sparse(const InstDesc *__restrict__ descs,
+                                                     const Tile *__restrict__ tiles, int32_t step)
+{
+    const Tile tl = group_tile(tiles);
+    const InstDesc &d = descs[tl.inst];
+    if (!d.active) return;
+    const int32_t t = step - d.start_step;
+    if (t < 1 || t > d.N) return;
+    const SolveState st = *d.st;
+    if (st.stopped) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t K = d.K, K1 = K + 1;
+    const SweepLds L = carve_lds(smem, kSparseW, K);
+    __shared__ int32_t s_jrow[kSparseW], s_jslot[kSparseW], s_jtabu[kSparseW],
+        s_jhel[kSparseW], s_rowof[kSparseW];
+    __shared__ int32_t s_t1c[kSparseW];
+    __shared__ int64_t s_t1d[kSparseW];
+    __shared__ int32_t s_nrows;
+    __shared__ Candidate s_red[BS / 64 + 1];
+    if (threadIdx.x < kSparseW)
+        sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
+    load_slot_inputs(d, t, L, false);
+    __syncthreads();
+    const int32_t nrows = s_nrows;
+    const int64_t base = (int64_t)tl.g * kSparseW * K1;
+    for (int32_t idx = threadIdx.x; idx < kSparseW * K1; idx += BS) {
+        const int32_t c = d.part_cov[base + idx];
+        const int64_t dd = d.part_dist[base + idx];
+        d.part_cov[base + idx] = 0;
+        d.part_dist[base + idx] = 0;
+        if (idx >= nrows * K1) continue;
+        const int32_t r = idx / K1, k = idx - r * K1;
+        if (k == 0) {
+            s_t1c[r] = c;
+            s_t1d[r] = dd;
+        } else {
+            L.bc[r * K + k - 1] = c;
+            L.bd[r * K + k - 1] = (u64)dd;
+        }
+    }
+    __syncthreads();
+    score_group<BS>(d, st, nrows, 1, t, tl.g, s_jrow, s_jtabu, s_jhel, L, s_t1c, s_t1d, s_red,
+                    s_jslot);
+}
+
 // Sums the chunk partials of one row group of a split instance and scores it.
 template <int J>
 __global__ __launch_bounds__(kBlock) void k_score(const InstDesc *__restrict__ descs,
@@ -1620,6 +1892,24 @@ InstPlan plan_instance(int32_t B, int32_t M, int32_t K, int J, int target_wg)
     return p;
 }
 
+InstPlan plan_sparse(int32_t B, int32_t M, int32_t K, int target_wg)
+{
+    InstPlan p;
+    const int32_t Mp = (M + 3) / 4 * 4;
+    p.sparse = 1;
+    p.nclosed = B - K;
+    p.ngroups = (B + kSparseW - 1) / kSparseW;
+    // mission chunks of at least 1,024 missions, enough to fill the GPU
+    int nsplit = std::max(1, (std::max(target_wg, 1) + p.ngroups - 1) / p.ngroups);
+    nsplit = std::min(nsplit, std::max(1, Mp / 1024));
+    nsplit = std::max(1, env_int("FS_SPARSE_SPLIT", nsplit));
+    int chunk = (Mp + nsplit - 1) / nsplit;
+    chunk = (chunk + 63) / 64 * 64;
+    p.nsplit = (Mp + chunk - 1) / chunk;
+    p.chunk = chunk;
+    return p;
+}
+
 size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
 {
     const size_t Mp = (size_t)(M + 3) / 4 * 4;
@@ -1638,7 +1928,15 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
     n += align_up(sizeof(Candidate) * std::max(p.ngroups, 1), 256);
     n += align_up(sizeof(SolveState), 256);
     n += 2 * align_up(4 * (size_t)K, 256);                      // best_open, best_sorted
-    if (p.nsplit > 1) {
+    if (p.sparse) {
+        const size_t lst = (size_t)p.ngroups * kSparseW * Mp;
+        n += align_up(4 * lst, 256) + align_up(lst, 256);   // sorted lists: costs, ids
+        n += align_up(4 * (size_t)B, 256);                  // base_slot
+        if (p.nsplit > 1) {   // the blocks' sums over mission chunks
+            const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
+            n += align_up(4 * np, 256) + align_up(8 * np, 256);
+        }
+    } else if (p.nsplit > 1) {
         const size_t np = (size_t)p.nsplit * p.nclosed * (K + 2);
         n += align_up(4 * np, 256) + align_up(8 * np, 256);
     }
@@ -1675,7 +1973,21 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.best_sorted = (int32_t *)take(4 * (size_t)K);
     d.part_cov = nullptr;
     d.part_dist = nullptr;
-    if (p.nsplit > 1) {
+    d.sparse = p.sparse;
+    d.lst_cost = nullptr;
+    d.lst_id = nullptr;
+    d.base_slot = nullptr;
+    if (p.sparse) {
+        const size_t lst = (size_t)p.ngroups * kSparseW * Mp;
+        d.lst_cost = (int32_t *)take(4 * lst);
+        d.lst_id = (unsigned char *)take(lst);
+        d.base_slot = (int32_t *)take(4 * (size_t)B);
+        if (p.nsplit > 1) {
+            const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
+            d.part_cov = (int32_t *)take(4 * np);
+            d.part_dist = (int64_t *)take(8 * np);
+        }
+    } else if (p.nsplit > 1) {
         const size_t np = (size_t)p.nsplit * p.nclosed * (K + 2);
         d.part_cov = (int32_t *)take(4 * np);
         d.part_dist = (int64_t *)take(8 * np);
@@ -1778,8 +2090,52 @@ fs_status sweep_rows(const EngineTables &t, const EngineConfig &c, int32_t step,
 }
 }  // namespace
 
+fs_status engine_sparse_prepare(const EngineTables &t, hipStream_t s)
+{
+    // (one instance: the descriptor's plan gives the grid of the list build)
+    InstDesc d;
+    FS_HIP(hipMemcpyAsync(&d, t.desc, sizeof d, hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    if (!d.sparse) return fail(FS_E_INTERNAL, "sparse preparation of a dense plan");
+    const int grid = d.ngroups * ((d.Mp + 63) / 64);
+    k_sparse_build<<<grid, kBlock, 0, s>>>(t.desc);
+    FS_HIP(hipGetLastError());
+    k_sparse_slots<<<std::max(1, std::min(64, (d.B + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+        t.desc);
+    FS_HIP(hipGetLastError());
+    if (d.nsplit > 1) {   // block sums start at zero; the score kernel clears them after use
+        const int64_t np = (int64_t)d.ngroups * kSparseW * (d.K + 1);
+        FS_TRY(engine_fill_i32(d.part_cov, np, 0, s));
+        FS_TRY(engine_fill_i64(d.part_dist, np, 0, s));
+    }
+    return FS_OK;
+}
+
+namespace {
+fs_status sweep_sparse(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
+{
+    const uint32_t lds = (uint32_t)sweep_lds_bytes(kSparseW, c.Kmax);
+    {
+        TimedLaunch tm(0);
+        launch_timed(k_sweep_sparse<kWideBlock>, dim3(t.nsweep), dim3(kWideBlock), lds, s,
+                     tm.start(), tm.stop(), t.desc, t.single ? nullptr : t.sweep, step);
+        FS_HIP(hipGetLastError());
+        tm.used();
+    }
+    if (t.nscore > 0) {   // (timed apart, as the "finalize" group)
+        TimedLaunch tm(2);
+        launch_timed(k_score_sparse<kWideBlock>, dim3(t.nscore), dim3(kWideBlock), lds, s,
+                     tm.start(), tm.stop(), t.desc, t.single ? nullptr : t.score, step);
+        FS_HIP(hipGetLastError());
+        tm.used();
+    }
+    return FS_OK;
+}
+}  // namespace
+
 fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
+    if (c.sparse) return sweep_sparse(t, c, step, s);
     if (t.nsweep > 0 || t.nscore > 0) FS_TRY(sweep_rows(t, c, step, s));
     if (t.nsweep_tall > 0) {
         EngineTables tall = t;

@@ -129,6 +129,29 @@ def write_traffic(fetch_db: str, write_db: str, kernel_re: str, copy_re: str, co
     return total
 
 
+def sparse_sweep_bytes(C, open_ids, width: int = 64) -> int:
+    """Bytes the sparse sweep needs in one iteration at placement open_ids:
+    for every block of `width` base ids and every mission, the block's sorted
+    list up to and including the first entry not below the mission's
+    second-nearest open cost (5 B per entry: int32 cost + uint8 id), plus the
+    mission's state (b1, b2, o1: 12 B) once per block.  C: host (B, M) int32."""
+    import numpy as np
+    C = np.asarray(C)
+    B, M = C.shape
+    rows = C[np.asarray(open_ids)]
+    if rows.shape[0] >= 2:
+        b2 = np.partition(rows, 1, axis=0)[1].astype(np.int64)
+    else:
+        b2 = np.full(M, 2**31 - 1, dtype=np.int64)
+    nb = (B + width - 1) // width
+    entries = 0
+    for q in range(nb):
+        blk = C[q * width:min(B, (q + 1) * width)]
+        below = (blk.astype(np.int64) < b2[None, :]).sum(axis=0)
+        entries += int(np.minimum(below + 1, width).sum())
+    return entries * 5 + nb * M * 12
+
+
 def read_traffic(path: str, workload: str):
     """Traffic per launch recorded in a summary, or None when it is missing,
     for another workload, or taken with a different kernel source."""
