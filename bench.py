@@ -105,13 +105,16 @@ def main():
     inst = synth.workload_instance(args.workload)
     dev = torch.device("cuda:0")
     bases = torch.from_numpy(inst.bases).to(dev)
-    missions = torch.from_numpy(inst.missions).to(dev)
+    hospitals = torch.from_numpy(inst.hospitals).to(dev)
+    mission_ph = torch.from_numpy(inst.mission_ph).to(dev)
     fs.lib()
 
     result = {}
 
     def step():
-        C, _ = fs.build_cost_table(bases, missions)
+        # the indexed builder: missions as hospital-id pairs (the same table,
+        # bitwise, as from the missions' coordinates)
+        C, _ = fs.build_cost_table_indexed(bases, hospitals, mission_ph)
         r = fs.tabu_solve(C, K, R, T, N, want_assign=True, want_trace=False)
         result["r"] = r
         result["C"] = C

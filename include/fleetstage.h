@@ -127,6 +127,22 @@ fs_status fs_build_cost_table(const double *base_latlon_deg, int32_t B,
                               double earth_radius_m, int32_t legs,
                               int32_t *C, int64_t ldc, double *Cf, void *stream);
 
+/* The same table from indexed missions (Section 3: a mission joins two known
+ * hospitals): hosp_latlon_deg (device, H x 2 degrees) and mission_ph
+ * (device, M x 2 int32: pickup and delivery hospital ids).  Mission m's
+ * coordinates are those of its two hospitals, and the result is bitwise the
+ * direct form's for those coordinates (each leg is the same haversine call
+ * and the legs are summed in the same order), computed with 2 B H + M
+ * haversines instead of 2 B M.  1 <= H <= 10,000 (two FP64 legs per hospital
+ * are staged on chip); FS_E_INVALID for ids outside [0, H) (after a check on
+ * the device; nothing is written then) and for the checks of
+ * fs_build_cost_table.  Synchronises the stream once (the id check). */
+fs_status fs_build_cost_table_indexed(const double *base_latlon_deg, int32_t B,
+                                      const double *hosp_latlon_deg, int32_t H,
+                                      const int32_t *mission_ph, int32_t M,
+                                      double earth_radius_m, int32_t legs, int32_t *C,
+                                      int64_t ldc, double *Cf, void *stream);
+
 /* Base ranking (Section 4.1, Algorithm 1's Top_Vals): row sums
  * S_b = sum_m C[b][m] (int64), and the K bases of smallest (S_b, b).
  *   open_out  device, K int32, the chosen ids in ascending id order

@@ -119,6 +119,71 @@ __global__ __launch_bounds__(kBlock) void k_cost_columns(const double *__restric
     }
 }
 
+// Indexed form: missions given as (pickup, delivery) hospital ids.  Per
+// mission: the pickup -> delivery leg from the hospitals' coordinates (the
+// same doubles as the direct form's mission coordinates) and a check of the
+// ids (bad ids are counted, and the table is not built).
+constexpr int kIndexedBlock = 1024;
+constexpr int32_t kIndexedMaxH = 10000;   // two FP64 legs per hospital in LDS
+
+__global__ __launch_bounds__(kBlock) void k_mission_legs(const double *__restrict__ hosp,
+                                                         int32_t H,
+                                                         const int32_t *__restrict__ ph,
+                                                         int32_t M, double two_r,
+                                                         double *__restrict__ pd,
+                                                         uint32_t *__restrict__ packed,
+                                                         int32_t *__restrict__ bad)
+{
+    const int32_t m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= M) return;
+    const int32_t p = ph[2 * (int64_t)m], d = ph[2 * (int64_t)m + 1];
+    if (p < 0 || p >= H || d < 0 || d >= H) {
+        atomicAdd(bad, 1);
+        pd[m] = 0.0;
+        packed[m] = 0;
+        return;
+    }
+    const double phi_p = hosp[2 * (int64_t)p] * kDeg2Rad, psi_p = hosp[2 * (int64_t)p + 1] * kDeg2Rad;
+    const double phi_d = hosp[2 * (int64_t)d] * kDeg2Rad, psi_d = hosp[2 * (int64_t)d + 1] * kDeg2Rad;
+    pd[m] = haversine(phi_p, psi_p, cos(phi_p), phi_d, psi_d, cos(phi_d), two_r);
+    packed[m] = (uint32_t)p | ((uint32_t)d << 16);
+}
+
+// One workgroup per base: the legs base -> hospital and hospital -> base for
+// every hospital in LDS (the direct form's two haversine calls with the same
+// arguments), then C[b][m] = (leg(b, p) + pd) + leg(d, b) for every mission,
+// in the direct form's order, so the table is bitwise the direct form's.
+__global__ __launch_bounds__(kIndexedBlock) void k_cost_indexed(
+    const double *__restrict__ bases, const double *__restrict__ hosp, int32_t H,
+    const double *__restrict__ pd, const uint32_t *__restrict__ packed, int32_t M, double two_r,
+    int32_t legs, int32_t *__restrict__ C, double *__restrict__ Cf, int64_t ldc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *to_h = reinterpret_cast<double *>(smem);   // base -> hospital
+    double *from_h = to_h + H;                         // hospital -> base
+    const int32_t b = blockIdx.x;
+    const double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
+    const double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
+    const double cos_b = cos(phi_b);
+    for (int32_t h = threadIdx.x; h < H; h += kIndexedBlock) {
+        const double phi_h = hosp[2 * (int64_t)h] * kDeg2Rad;
+        const double psi_h = hosp[2 * (int64_t)h + 1] * kDeg2Rad;
+        const double cos_h = cos(phi_h);
+        to_h[h] = haversine(phi_b, psi_b, cos_b, phi_h, psi_h, cos_h, two_r);
+        from_h[h] = haversine(phi_h, psi_h, cos_h, phi_b, psi_b, cos_b, two_r);
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)b * ldc;
+    for (int32_t m = threadIdx.x; m < M; m += kIndexedBlock) {
+        const uint32_t q = packed[m];
+        const double bp = to_h[q & 0xFFFF];
+        const double db = from_h[q >> 16];
+        const double v = (legs == 3) ? (bp + pd[m]) + db : bp + db;
+        C[row + m] = (int32_t)rint(v);
+        if (Cf) Cf[row + m] = v;
+    }
+}
+
 }  // namespace
 
 fs_status launch_cost_columns(const double *bases, int32_t B, const int32_t *ids,
@@ -171,5 +236,57 @@ extern "C" fs_status fs_build_cost_table(const double *base_latlon_deg, int32_t 
     k_cost_table<<<g2, kBlock, 0, s>>>(base_latlon_deg, B, M, two_r, legs, mp, C, Cf, ldc);
     FS_HIP(hipGetLastError());
     FS_HIP(hipFreeAsync(buf, s));
+    return FS_OK;
+}
+
+extern "C" fs_status fs_build_cost_table_indexed(const double *base_latlon_deg, int32_t B,
+                                                 const double *hosp_latlon_deg, int32_t H,
+                                                 const int32_t *mission_ph, int32_t M,
+                                                 double earth_radius_m, int32_t legs, int32_t *C,
+                                                 int64_t ldc, double *Cf, void *stream)
+{
+    using namespace fs;
+    if (!base_latlon_deg || !hosp_latlon_deg || !mission_ph || !C)
+        return fail(FS_E_INVALID, "NULL coordinate, id or output pointer");
+    if (B < 1 || M < 1 || H < 1)
+        return fail(FS_E_INVALID, "B=%d, H=%d, M=%d: all must be >= 1", B, H, M);
+    if (H > kIndexedMaxH)
+        return fail(FS_E_INVALID, "H=%d hospitals: the indexed form takes at most %d", H,
+                    kIndexedMaxH);
+    if (ldc < M) return fail(FS_E_INVALID, "row pitch ldc=%lld < M=%d", (long long)ldc, M);
+    if (legs != 2 && legs != 3) return fail(FS_E_INVALID, "legs=%d: must be 2 or 3", legs);
+    if (!(earth_radius_m >= 0.0)) return fail(FS_E_INVALID, "negative or NaN radius");
+    const double r = earth_radius_m == 0.0 ? 6371000.0 : earth_radius_m;
+    if (r > 1.1e8) return fail(FS_E_INVALID, "radius %.3g m: costs would overflow int32", r);
+    hipStream_t s = (hipStream_t)stream;
+    const double two_r = 2.0 * r;
+    char *buf = nullptr;
+    const size_t pd_bytes = sizeof(double) * (size_t)M, pk_bytes = sizeof(uint32_t) * (size_t)M;
+    FS_HIP(hipMallocAsync((void **)&buf, pd_bytes + pk_bytes + 256, s));
+    double *pd = (double *)buf;
+    uint32_t *packed = (uint32_t *)(buf + pd_bytes);
+    int32_t *bad = (int32_t *)(buf + pd_bytes + pk_bytes);   // (12 M bytes: 4-aligned)
+    int32_t nbad = 0;
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) {
+        k_mission_legs<<<(M + kBlock - 1) / kBlock, kBlock, 0, s>>>(hosp_latlon_deg, H, mission_ph,
+                                                                   M, two_r, pd, packed, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && nbad == 0) {
+        const size_t lds = 2 * sizeof(double) * (size_t)H;
+        e = hipFuncSetAttribute((const void *)k_cost_indexed,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess) {
+            k_cost_indexed<<<B, kIndexedBlock, lds, s>>>(base_latlon_deg, hosp_latlon_deg, H, pd,
+                                                         packed, M, two_r, legs, C, Cf, ldc);
+            e = hipGetLastError();
+        }
+    }
+    (void)hipFreeAsync(buf, s);
+    if (e != hipSuccess) return fail(FS_E_DEVICE, "indexed cost table: %s", hipGetErrorString(e));
+    if (nbad) return fail(FS_E_INVALID, "%d missions name a hospital outside [0, %d)", nbad, H);
     return FS_OK;
 }

@@ -98,6 +98,9 @@ def lib():
     L.fs_version.argtypes = []
     L.fs_build_cost_table.restype = i32
     L.fs_build_cost_table.argtypes = [vp, i32, vp, i32, f64, i32, vp, i64, vp, vp]
+    L.fs_build_cost_table_indexed.restype = i32
+    L.fs_build_cost_table_indexed.argtypes = [vp, i32, vp, i32, vp, i32, f64, i32, vp, i64, vp,
+                                              vp]
     L.fs_rank_bases.restype = i32
     L.fs_rank_bases.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp]
     L.fs_move_scores.restype = i32
@@ -205,6 +208,25 @@ def build_cost_table(bases, missions, earth_radius_m: float = 0.0, legs: int = 3
                                      _ptr(missions, torch.float64), M, float(earth_radius_m),
                                      int(legs), _ptr(C), ldc, _ptr(Cf), _stream(stream)))
     # (B, M) views of the padded rows: the other calls read M and ldc from them
+    return C[:, :M], (Cf[:, :M] if Cf is not None else None)
+
+
+def build_cost_table_indexed(bases, hospitals, mission_ph, earth_radius_m: float = 0.0,
+                             legs: int = 3, ldc: int | None = None, want_cf: bool = False,
+                             stream=None):
+    """As build_cost_table, from hospital coordinates (H, 2) float64 and the
+    missions' (pickup, delivery) hospital ids (M, 2) int32, all on the
+    device; bitwise the direct form's table."""
+    B, H, M = int(bases.shape[0]), int(hospitals.shape[0]), int(mission_ph.shape[0])
+    ldc = (M + 3) // 4 * 4 if ldc is None else int(ldc)
+    dev = bases.device
+    C = torch.empty((B, ldc), dtype=torch.int32, device=dev)
+    Cf = torch.empty((B, ldc), dtype=torch.float64, device=dev) if want_cf else None
+    _check(lib().fs_build_cost_table_indexed(_ptr(bases, torch.float64), B,
+                                             _ptr(hospitals, torch.float64), H,
+                                             _ptr(mission_ph, torch.int32), M,
+                                             float(earth_radius_m), int(legs), _ptr(C), ldc,
+                                             _ptr(Cf), _stream(stream)))
     return C[:, :M], (Cf[:, :M] if Cf is not None else None)
 
 
