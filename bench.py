@@ -157,11 +157,12 @@ def main():
         sweep_bytes = (B - K) * M * 4 + 12 * M
     sweep_avg_s = (sweep_ms / max(sweep_n, 1)) / 1e3
     achieved = sweep_bytes / sweep_avg_s / 1e9 if sweep_n else None
-    traffic = None if sparse else profiling.read_traffic(
-        os.path.join(ROOT, "profiles", f"k_sweep_{args.workload}_traffic.md"), args.workload)
+    kname = "k_sweep_sparse" if sparse else "k_sweep"
+    traffic = profiling.read_traffic(
+        os.path.join(ROOT, "profiles", f"{kname}_{args.workload}_traffic.md"), args.workload)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                "kernel": "k_sweep_sparse" if sparse else "k_sweep",
+                "kernel": kname,
                 "bytes_per_launch": sweep_bytes,
                 "avg_launch_us": sweep_avg_s * 1e6, "launches": sweep_n}
 
