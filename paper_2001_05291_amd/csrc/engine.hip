@@ -49,6 +49,26 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64;
+// Global-memory views of device pointers: loads through them are global
+// loads, counted by vmcnt alone, so waiting for an LDS result does not also
+// wait for them (generic loads count against both counters).
+typedef const __attribute__((address_space(1))) int32_t gi32;
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+// Whole-struct store through a global view, one dword at a time (merged
+// into wide stores by the compiler).
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+    __attribute__((address_space(1))) int32_t *q = gptr(reinterpret_cast<int32_t *>(p));
+    const int32_t *w = reinterpret_cast<const int32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) q[i] = w[i];
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -173,14 +193,21 @@ __device__ Candidate block_best(Candidate c, Candidate *s_red /* BS/64 + 1 */)
     __syncthreads();
     if (lane == 0) s_red[wave] = c;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        Candidate b = s_red[0];
-        for (int w = 1; w < BS / 64; ++w)
-            if (cand_better<KEYED>(s_red[w], b)) b = s_red[w];
-        s_red[BS / 64] = b;
+    // the waves' bests reduced across the lanes of the first wave (kept in
+    // registers: a loop over s_red in one thread spills the candidate)
+    constexpr int NW = BS / 64;
+    static_assert((NW & (NW - 1)) == 0, "block size: a power-of-two number of waves");
+    if (wave == 0) {
+        Candidate b = lane < NW ? s_red[lane] : no_cand();
+#pragma unroll
+        for (int off = NW / 2; off > 0; off >>= 1) {
+            const Candidate o = shfl_xor_cand<KEYED>(b, off);
+            if (cand_better<KEYED>(o, b)) b = o;
+        }
+        if (lane == 0) s_red[NW] = b;
     }
     __syncthreads();
-    return s_red[BS / 64];
+    return s_red[NW];
 }
 
 // G (k = 0) or L_{k-1}: sum of the accumulator stripes.
@@ -447,7 +474,7 @@ __device__ void write_record(const InstDesc &d, int32_t t, const SolveState &s, 
     rec.best_cov = s.best_cov;
     rec.cur_dist = s.cur_dist;
     rec.best_dist = s.best_dist;
-    d.trace[t - 1] = rec;
+    gstore(d.trace + (t - 1), rec);
 }
 
 // One workgroup = 64 missions of one instance (one per lane).
@@ -743,37 +770,45 @@ __global__ __launch_bounds__(kBlock) void k_init_score(const InstDesc *__restric
 // t1c[0 .. NC-1], t1d[0 .. NC-1]: the row's common term; with NC = 2 split
 // over ordinary [0] and rotary-only [1] missions (o1 bit 16; a homogeneous
 // fleet has none, NC = 1).  The bin is the low 16 bits of o1.
+// An element below b2 (the caller has checked it).
+template <int NC>
+__device__ __forceinline__ void visit_hit(int32_t c, int32_t b1, int32_t o1, int32_t g1c,
+                                          int32_t g1d, int32_t g2c, int32_t g2d, int32_t R,
+                                          int32_t *t1c, int64_t *t1d, int32_t *__restrict__ bc,
+                                          u64 *__restrict__ bd)
+{
+    const int32_t v1 = min(c, b1);
+    const int32_t u = max(c, b1);
+    const int32_t cv = v1 <= R;
+    const int32_t tc = cv - g1c;
+    const int32_t td = (cv ? v1 : 0) - g1d;
+    if constexpr (NC == 1) {
+        t1c[0] += tc;
+        t1d[0] += (int64_t)td;
+    } else {
+        const bool rot_only = (o1 >> 16) != 0;
+        t1c[0] += rot_only ? 0 : tc;
+        t1c[1] += rot_only ? tc : 0;
+        t1d[0] += (int64_t)(rot_only ? 0 : td);
+        t1d[1] += (int64_t)(rot_only ? td : 0);
+    }
+    const int32_t cu = u <= R;
+    const int32_t dc = cu - g2c;
+    const int32_t dd = (cu ? u : 0) - g2d;
+    const int32_t slot = o1 & 0xFFFF;
+    if (dc | dd) {
+        atomicAdd(bc + slot, dc);
+        atomicAdd(bd + slot, (u64)(int64_t)dd);
+    }
+}
+
 template <int NC>
 __device__ __forceinline__ void visit(int32_t c, int32_t b1, int32_t b2, int32_t o1, int32_t g1c,
                                       int32_t g1d, int32_t g2c, int32_t g2d, int32_t R,
                                       int32_t *t1c, int64_t *t1d, int32_t *__restrict__ bc,
                                       u64 *__restrict__ bd)
 {
-    if (c < b2) {
-        const int32_t v1 = min(c, b1);
-        const int32_t u = max(c, b1);
-        const int32_t cv = v1 <= R;
-        const int32_t tc = cv - g1c;
-        const int32_t td = (cv ? v1 : 0) - g1d;
-        if constexpr (NC == 1) {
-            t1c[0] += tc;
-            t1d[0] += (int64_t)td;
-        } else {
-            const bool rot_only = (o1 >> 16) != 0;
-            t1c[0] += rot_only ? 0 : tc;
-            t1c[1] += rot_only ? tc : 0;
-            t1d[0] += (int64_t)(rot_only ? 0 : td);
-            t1d[1] += (int64_t)(rot_only ? td : 0);
-        }
-        const int32_t cu = u <= R;
-        const int32_t dc = cu - g2c;
-        const int32_t dd = (cu ? u : 0) - g2d;
-        const int32_t slot = o1 & 0xFFFF;
-        if (dc | dd) {
-            atomicAdd(bc + slot, dc);
-            atomicAdd(bd + slot, (u64)(int64_t)dd);
-        }
-    }
+    if (c < b2) visit_hit<NC>(c, b1, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
 }
 
 // LDS of the sweep / score kernels for J rows and up to Kmax slots.
@@ -978,11 +1013,17 @@ __device__ __forceinline__ void visit_queued(const InstDesc &d, const QueueRow &
                                              int32_t R, int32_t *t1c, int64_t *t1d,
                                              int32_t *__restrict__ bc, u64 *__restrict__ bd)
 {
+    // every queued element is below its b2: the three gathers go out
+    // together and nothing waits on b2 alone
     const int32_t c = qr.c[at], m = qr.m[at];
-    const int32_t b1 = d.b1[m], b2 = d.b2[m], o1 = d.o1[m];
+    const int32_t b1 = ((const gi32 *)d.b1)[m], b2 = ((const gi32 *)d.b2)[m],
+                  o1 = ((const gi32 *)d.o1)[m];
+    // (an empty use of all three, so that no gather is moved into the
+    // branches below and waited for on its own)
+    asm volatile("" ::"v"(b1), "v"(b2), "v"(o1));
     const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
     const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
-    visit<NC>(c, b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
+    visit_hit<NC>(c, b1, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
 }
 
 template <int BS, int J, int U, bool NT, int NC>
@@ -1082,7 +1123,7 @@ __device__ __forceinline__ void visit_queued4(const QueueRow4 &qr, int32_t at, i
     const int32_t c = qr.c[at], b1 = qr.b1[at], b2 = qr.b2[at], o1 = qr.o1[at];
     const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
     const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
-    visit<NC>(c, b1, b2, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
+    visit_hit<NC>(c, b1, o1, g1c, g1d, g2c, g2d, R, t1c, t1d, bc, bd);
 }
 
 template <int BS, int J, int U, bool NT, int NC>
@@ -1378,9 +1419,11 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     const InstDesc &d = descs[0];
     const int32_t nmg = (d.Mp + 63) / 64;
     const int32_t q = (int32_t)blockIdx.x / nmg, mg = (int32_t)blockIdx.x - q * nmg;
+    // (row pitches of 65 words and 68 bytes: a wave writing one column
+    // touches a different bank in every lane)
     __shared__ int32_t s_c[kSparseW][65];
-    __shared__ int32_t s_cost[kSparseW][64];
-    __shared__ unsigned char s_id[kSparseW][64];
+    __shared__ int32_t s_cost[kSparseW][65];
+    __shared__ unsigned char s_id[kSparseW][68];
     for (int32_t idx = threadIdx.x; idx < kSparseW * 64; idx += kBlock) {
         const int32_t l = idx >> 6, mm = idx & 63;
         const int32_t b = q * kSparseW + l, m = mg * 64 + mm;
@@ -1388,20 +1431,34 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i = 0; i < 64 / (kBlock / 64); ++i) {
-        const int32_t mm = wave * (64 / (kBlock / 64)) + i;
-        uint64_t key = ((uint64_t)((uint32_t)s_c[lane][mm] ^ 0x80000000u) << 6) | (uint64_t)lane;
+    // four missions' sorts interleaved, so that each exchange's latency is
+    // covered by the other three
+    constexpr int PER_WAVE = 64 / (kBlock / 64), IL = 4;
+    for (int i0 = 0; i0 < PER_WAVE; i0 += IL) {
+        uint64_t key[IL];
+#pragma unroll
+        for (int q = 0; q < IL; ++q) {
+            const int32_t mm = wave * PER_WAVE + i0 + q;
+            key[q] = ((uint64_t)((uint32_t)s_c[lane][mm] ^ 0x80000000u) << 6) | (uint64_t)lane;
+        }
 #pragma unroll
         for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
             for (int j = k >> 1; j > 0; j >>= 1) {
-                const uint64_t other = __shfl_xor(key, j, 64);
                 const bool up = (lane & k) == 0, lower = (lane & j) == 0;
-                key = (lower == up) ? min(key, other) : max(key, other);
+#pragma unroll
+                for (int q = 0; q < IL; ++q) {
+                    const uint64_t other = __shfl_xor(key[q], j, 64);
+                    key[q] = (lower == up) ? min(key[q], other) : max(key[q], other);
+                }
             }
         }
-        s_cost[lane][mm] = (int32_t)((uint32_t)(key >> 6) ^ 0x80000000u);
-        s_id[lane][mm] = (unsigned char)(key & 63);
+#pragma unroll
+        for (int q = 0; q < IL; ++q) {
+            const int32_t mm = wave * PER_WAVE + i0 + q;
+            s_cost[lane][mm] = (int32_t)((uint32_t)(key[q] >> 6) ^ 0x80000000u);
+            s_id[lane][mm] = (unsigned char)(key[q] & 63);
+        }
     }
     __syncthreads();
     for (int32_t idx = threadIdx.x; idx < kSparseW * 64; idx += kBlock) {
