@@ -58,8 +58,19 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p)
 {
     return (__attribute__((address_space(1))) T *)p;
 }
-// Whole-struct store through a global view, one dword at a time (merged
-// into wide stores by the compiler).
+// Whole-struct load / store through a global view, one dword at a time
+// (merged into wide accesses by the compiler).
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+    T out;
+    const gi32 *q = (const gi32 *)p;
+    int32_t *o = reinterpret_cast<int32_t *>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
+    return out;
+}
 template <typename T>
 __device__ __forceinline__ void gstore(T *p, const T &v)
 {
@@ -514,22 +525,51 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     __shared__ int32_t s_improved;
 
     if (t >= 1) {
-        if (st->stopped) {
+        // The stop flag, this thread's first candidates and its open slot go
+        // out together and are waited for once.  (No closed base: no row
+        // group and no move; the candidate array always holds one entry.)
+        const int32_t ncand = d.ngroups;
+        const int32_t stopped = gptr(st)->stopped;
+        constexpr int CU = 4;
+        const int32_t qlast = ncand > 0 ? ncand - 1 : 0;
+        Candidate cq[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            cq[u] = gload(d.cand + min((int32_t)threadIdx.x + u * kBlock, qlast));
+        const int32_t k0 = (int32_t)threadIdx.x < K ? (int32_t)threadIdx.x : 0;
+        const int32_t op0 = gptr(d.open)[k0];
+        const int32_t or0 = TY ? gptr(d.open_rot)[k0] : 0;
+        // (empty uses, so that no part of these loads is moved past the
+        // stop check or into the comparisons' branches)
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            asm volatile("" ::"v"(cq[u].cov), "v"(cq[u].i_base), "v"(cq[u].j_base),
+                         "v"(cq[u].slots), "v"(cq[u].dist), "v"(cq[u].key));
+        asm volatile("" ::"v"(op0), "v"(or0), "v"(stopped));
+        if (stopped) {
             // local search ended earlier: the iteration makes no move
             if (leader && threadIdx.x == 0) write_record(d, t, *st, 0, -1, -1);
             return;
         }
-        // (no closed base: no row group and no move)
-        const int32_t ncand = d.ngroups;
         Candidate best = no_cand();
-        for (int32_t q = threadIdx.x; q < ncand; q += kBlock) {
-            const Candidate c = d.cand[q];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const bool in = (int32_t)threadIdx.x + u * kBlock < ncand;
+            if (in && (d.mode >= 2 ? cand_better<true>(cq[u], best)
+                                   : cand_better<false>(cq[u], best)))
+                best = cq[u];
+        }
+        for (int32_t q = threadIdx.x + CU * kBlock; q < ncand; q += kBlock) {
+            const Candidate c = gload(d.cand + q);
             if (d.mode >= 2 ? cand_better<true>(c, best) : cand_better<false>(c, best)) best = c;
         }
-        const int32_t *cur_open = d.open;
-        for (int k = threadIdx.x; k < K; k += kBlock) {
-            s_open[k] = cur_open[k];
-            if (TY) s_rot[k] = d.open_rot[k];
+        if ((int32_t)threadIdx.x < K) {
+            s_open[threadIdx.x] = op0;
+            if (TY) s_rot[threadIdx.x] = or0;
+        }
+        for (int k = threadIdx.x + kBlock; k < K; k += kBlock) {
+            s_open[k] = gptr(d.open)[k];
+            if (TY) s_rot[k] = gptr(d.open_rot)[k];
         }
         // barriers: s_open complete too
         best = d.mode >= 2 ? block_best<kBlock, true>(best, s_red)
