@@ -1449,6 +1449,59 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
 // dense sweep's (the same integer arithmetic on the same elements), so the
 // scores are identical.
 
+// The value of lane (lane ^ J) of a full wave.  J = 1, 2 and 8 stay in the
+// vector ALU (DPP quad permutes and a rotate by 8 within each 16-lane row);
+// the other distances go through the LDS crossbar.  Every lane must be
+// active.
+template <int J>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v)
+{
+    if constexpr (J == 1 || J == 2 || J == 8) {
+        constexpr int kCtrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
+        const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)v, kCtrl, 0xF, 0xF, false);
+        const int32_t hi =
+            __builtin_amdgcn_update_dpp(0, (int32_t)(v >> 32), kCtrl, 0xF, 0xF, false);
+        return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    } else {
+        return __shfl_xor(v, J, 64);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v)
+{
+    if constexpr (J == 1 || J == 2 || J == 8) {
+        constexpr int kCtrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, kCtrl, 0xF, 0xF, false);
+    } else {
+        return (uint32_t)__shfl_xor((int32_t)v, J, 64);
+    }
+}
+
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int j)
+{
+    switch (j) {   // (j is a constant once the sorting network is unrolled)
+    case 1: return lane_xor32<1>(v);
+    case 2: return lane_xor32<2>(v);
+    case 4: return lane_xor32<4>(v);
+    case 8: return lane_xor32<8>(v);
+    case 16: return lane_xor32<16>(v);
+    default: return lane_xor32<32>(v);
+    }
+}
+
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int j)
+{
+    switch (j) {   // (j is a constant once the sorting network is unrolled)
+    case 1: return lane_xor64<1>(v);
+    case 2: return lane_xor64<2>(v);
+    case 4: return lane_xor64<4>(v);
+    case 8: return lane_xor64<8>(v);
+    case 16: return lane_xor64<16>(v);
+    default: return lane_xor64<32>(v);
+    }
+}
+
 // Sorted lists of one block x 64 missions: the C tile is staged in LDS, each
 // wave sorts a mission's 64 (cost, local id) keys across its lanes (bitonic,
 // ascending; the sign bit is flipped so that the unsigned key order is the
@@ -1463,24 +1516,75 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     // touches a different bank in every lane)
     __shared__ int32_t s_c[kSparseW][65];
     __shared__ int32_t s_cost[kSparseW][65];
-    __shared__ unsigned char s_id[kSparseW][68];
-    for (int32_t idx = threadIdx.x; idx < kSparseW * 64; idx += kBlock) {
-        const int32_t l = idx >> 6, mm = idx & 63;
-        const int32_t b = q * kSparseW + l, m = mg * 64 + mm;
-        s_c[l][mm] = (b < d.B && m < d.M) ? d.C[(int64_t)b * d.ldc + m] : INT32_MAX;
+    __shared__ __align__(16) unsigned char s_id[kSparseW][68];
+    // every load of the tile in flight before the first LDS write (each
+    // thread: one mission, every fourth base of the block)
+    constexpr int PER_THREAD = kSparseW * 64 / kBlock;
+    const gi32 *C = (const gi32 *)d.C;
+    const int64_t ldc = d.ldc;
+    const int32_t B = d.B, m = mg * 64 + (int32_t)(threadIdx.x & 63);
+    const int32_t l0 = (int32_t)threadIdx.x >> 6;
+    const bool m_in = m < d.M;
+    const gi32 *col = C + (m_in ? m : 0);
+    int32_t v[PER_THREAD];
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+        const int32_t b = q * kSparseW + l0 + i * (kBlock / 64);
+        const bool in = m_in && b < B;
+        v[i] = col[in ? (int64_t)b * ldc : 0];
+        v[i] = in ? v[i] : INT32_MAX;
     }
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) s_c[l0 + i * (kBlock / 64)][threadIdx.x & 63] = v[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // four missions' sorts interleaved, so that each exchange's latency is
     // covered by the other three
+    // (narrow keys: when every cost of the four missions lies in
+    // [0, 2^26 - 1) or is the sentinel, (cost << 6 | id) fits 32 bits with
+    // the sentinel as 2^26 - 1, in the same order; a haversine round trip is
+    // below 6.1e7 m < 2^26 - 1, so real tables take this path)
+    constexpr uint32_t kNarrowTop = (1u << 26) - 1;
     constexpr int PER_WAVE = 64 / (kBlock / 64), IL = 4;
     for (int i0 = 0; i0 < PER_WAVE; i0 += IL) {
-        uint64_t key[IL];
+        int32_t cst[IL];
+        bool fits = true;
 #pragma unroll
         for (int q = 0; q < IL; ++q) {
-            const int32_t mm = wave * PER_WAVE + i0 + q;
-            key[q] = ((uint64_t)((uint32_t)s_c[lane][mm] ^ 0x80000000u) << 6) | (uint64_t)lane;
+            cst[q] = s_c[lane][wave * PER_WAVE + i0 + q];
+            fits = fits && (cst[q] == INT32_MAX || (uint32_t)cst[q] < kNarrowTop);
         }
+        if (__builtin_amdgcn_ballot_w64(!fits) == 0) {
+            uint32_t key[IL];
+#pragma unroll
+            for (int q = 0; q < IL; ++q)
+                key[q] = ((cst[q] == INT32_MAX ? kNarrowTop : (uint32_t)cst[q]) << 6) |
+                         (uint32_t)lane;
+#pragma unroll
+            for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+#pragma unroll
+                    for (int q = 0; q < IL; ++q) {
+                        const uint32_t other = lane_xor32(key[q], j);
+                        key[q] = (lower == up) ? min(key[q], other) : max(key[q], other);
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < IL; ++q) {
+                const int32_t mm = wave * PER_WAVE + i0 + q;
+                const uint32_t c = key[q] >> 6;
+                s_cost[lane][mm] = c == kNarrowTop ? INT32_MAX : (int32_t)c;
+                s_id[lane][mm] = (unsigned char)(key[q] & 63);
+            }
+            continue;
+        }
+        uint64_t key[IL];
+#pragma unroll
+        for (int q = 0; q < IL; ++q)
+            key[q] = ((uint64_t)((uint32_t)cst[q] ^ 0x80000000u) << 6) | (uint64_t)lane;
 #pragma unroll
         for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -1488,7 +1592,7 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
                 const bool up = (lane & k) == 0, lower = (lane & j) == 0;
 #pragma unroll
                 for (int q = 0; q < IL; ++q) {
-                    const uint64_t other = __shfl_xor(key[q], j, 64);
+                    const uint64_t other = lane_xor64(key[q], j);
                     key[q] = (lower == up) ? min(key[q], other) : max(key[q], other);
                 }
             }
@@ -1501,12 +1605,23 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
         }
     }
     __syncthreads();
-    for (int32_t idx = threadIdx.x; idx < kSparseW * 64; idx += kBlock) {
-        const int32_t r = idx >> 6, mm = idx & 63, m = mg * 64 + mm;
-        if (m < d.Mp) {
-            const int64_t at = ((int64_t)q * kSparseW + r) * d.Mp + m;
-            d.lst_cost[at] = s_cost[r][mm];
-            d.lst_id[at] = s_id[r][mm];
+    // four consecutive missions of one rank per thread and step: one 16-byte
+    // store of costs and one 4-byte store of ids (Mp is a multiple of 4, so a
+    // quad lies wholly inside or outside the padded mission range, and every
+    // quad's address is 16- and 4-byte aligned)
+    const int64_t Mp = d.Mp;
+    for (int32_t u = threadIdx.x; u < kSparseW * 16; u += kBlock) {
+        const int32_t r = u >> 4, mm = (u & 15) * 4, m = mg * 64 + mm;
+        if (m < Mp) {
+            const int64_t at = ((int64_t)q * kSparseW + r) * Mp + m;
+            v4i c;
+            c[0] = s_cost[r][mm];
+            c[1] = s_cost[r][mm + 1];
+            c[2] = s_cost[r][mm + 2];
+            c[3] = s_cost[r][mm + 3];
+            *reinterpret_cast<v4i *>(d.lst_cost + at) = c;
+            *reinterpret_cast<uint32_t *>(d.lst_id + at) =
+                *reinterpret_cast<const uint32_t *>(&s_id[r][mm]);
         }
     }
 }

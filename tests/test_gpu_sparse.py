@@ -84,6 +84,29 @@ def test_move_scores_random_tables_with_ties():
         check_scores(C, S, R, ldc=M + int(rng.integers(0, 4)), split=int(rng.integers(1, 4)))
 
 
+def wide_table(rng, B, M, frac):
+    """Small costs with a fraction at and above 2^26 - 2, where the list
+    sort switches from 32-bit to 64-bit keys (2^26 - 2 still narrow, 2^26 - 1
+    and above wide)."""
+    C = rng.integers(1, 5000, size=(B, M)).astype(np.int64)
+    big = rng.random((B, M)) < frac
+    C[big] = rng.integers(2**26 - 2, 2**31 - 2, size=int(big.sum()))
+    C[0, 0] = 2**26 - 1
+    return C.astype(np.int32)
+
+
+def test_move_scores_wide_costs():
+    rng = np.random.default_rng(49)
+    for trial in range(8):
+        B = int(rng.integers(70, 200))
+        M = int(rng.integers(100, 700))
+        C = wide_table(rng, B, M, 0.5 if trial % 2 else 0.01)
+        K = int(rng.integers(1, 40))
+        R = int(rng.integers(0, 2**31 - 2))
+        S = rng.choice(B, K, replace=False).tolist()
+        check_scores(C, S, R, ldc=M + int(rng.integers(0, 4)), split=int(rng.integers(1, 4)))
+
+
 def run_both(C, K, R, T, N, mode=0, seed=0, ldc=None, split=None):
     B, M = C.shape
     kv = dict(FS_SPARSE=1)
@@ -132,6 +155,13 @@ def test_random_instances():
         g, o = run_both(C, K, R, int(rng.integers(0, 9)), int(rng.integers(0, 40)),
                         ldc=M + int(rng.integers(0, 4)), split=int(rng.integers(1, 4)))
         assert_same(g, o, C, R)
+
+
+def test_tabu_trace_wide_costs():
+    rng = np.random.default_rng(50)
+    C = wide_table(rng, 150, 900, 0.05)
+    g, o = run_both(C, 9, 2**30, 5, 60, ldc=901, split=2)
+    assert_same(g, o, C, 2**30)
 
 
 def test_default_rule_picks_sparse_for_many_closed_bases():
