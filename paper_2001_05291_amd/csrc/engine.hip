@@ -469,6 +469,131 @@ __global__ __launch_bounds__(kBlock) void k_fleet_lists(const InstDesc *__restri
         d.closed_hel[q] = d.base_hel[d.closed[q]] != 0;
 }
 
+// The value of lane (lane ^ J) of a full wave.  J = 1, 2 and 8 stay in the
+// vector ALU (DPP quad permutes and a rotate by 8 within each 16-lane row);
+// the other distances go through the LDS crossbar.  Every lane must be
+// active.
+template <int J>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v)
+{
+    if constexpr (J == 1 || J == 2 || J == 8) {
+        constexpr int kCtrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
+        const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)v, kCtrl, 0xF, 0xF, false);
+        const int32_t hi =
+            __builtin_amdgcn_update_dpp(0, (int32_t)(v >> 32), kCtrl, 0xF, 0xF, false);
+        return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    } else {
+        return __shfl_xor(v, J, 64);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v)
+{
+    if constexpr (J == 1 || J == 2 || J == 8) {
+        constexpr int kCtrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, kCtrl, 0xF, 0xF, false);
+    } else {
+        return (uint32_t)__shfl_xor((int32_t)v, J, 64);
+    }
+}
+
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int j)
+{
+    switch (j) {   // (j is a constant once the sorting network is unrolled)
+    case 1: return lane_xor32<1>(v);
+    case 2: return lane_xor32<2>(v);
+    case 4: return lane_xor32<4>(v);
+    case 8: return lane_xor32<8>(v);
+    case 16: return lane_xor32<16>(v);
+    default: return lane_xor32<32>(v);
+    }
+}
+
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int j)
+{
+    switch (j) {   // (j is a constant once the sorting network is unrolled)
+    case 1: return lane_xor64<1>(v);
+    case 2: return lane_xor64<2>(v);
+    case 4: return lane_xor64<4>(v);
+    case 8: return lane_xor64<8>(v);
+    case 16: return lane_xor64<16>(v);
+    default: return lane_xor64<32>(v);
+    }
+}
+
+// The refresh's reductions: the butterflies above with DPP moves at lane
+// distances 1, 2 and 8.  (Measured: 0.4 us off each refresh at the medium
+// workload; the same change in the sweep's scoring made the sparse sweep at
+// the large workload 35% slower and the dense one 0.4 us slower, so the
+// sweeps keep the LDS-crossbar forms.)  Every lane of the wave must be
+// active.
+template <bool KEYED, int OFF>
+__device__ __forceinline__ void best_step_x(Candidate &c)
+{
+    Candidate o;
+    o.cov = (int32_t)lane_xor32<OFF>((uint32_t)c.cov);
+    o.i_base = (int32_t)lane_xor32<OFF>((uint32_t)c.i_base);
+    o.j_base = (int32_t)lane_xor32<OFF>((uint32_t)c.j_base);
+    o.slots = lane_xor32<OFF>(c.slots);
+    o.dist = (int64_t)lane_xor64<OFF>((uint64_t)c.dist);
+    o.key = KEYED ? lane_xor64<OFF>(c.key) : c.key;
+    if (cand_better<KEYED>(o, c)) c = o;
+}
+
+template <bool KEYED, int N>
+__device__ __forceinline__ Candidate wave_best_x(Candidate c)
+{
+    if constexpr (N > 32) best_step_x<KEYED, 32>(c);
+    if constexpr (N > 16) best_step_x<KEYED, 16>(c);
+    if constexpr (N > 8) best_step_x<KEYED, 8>(c);
+    if constexpr (N > 4) best_step_x<KEYED, 4>(c);
+    if constexpr (N > 2) best_step_x<KEYED, 2>(c);
+    if constexpr (N > 1) best_step_x<KEYED, 1>(c);
+    return c;
+}
+
+template <int BS, bool KEYED>
+__device__ Candidate block_best_x(Candidate c, Candidate *s_red /* BS/64 + 1 */)
+{
+    constexpr int NW = BS / 64;
+    static_assert((NW & (NW - 1)) == 0, "block size: a power-of-two number of waves");
+    c = wave_best_x<KEYED, 64>(c);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) s_red[wave] = c;
+    __syncthreads();
+    if (wave == 0) {
+        Candidate b = lane < NW ? s_red[lane] : no_cand();
+        b = wave_best_x<KEYED, NW>(b);
+        if (lane == 0) s_red[NW] = b;
+    }
+    __syncthreads();
+    return s_red[NW];
+}
+
+__device__ __forceinline__ int32_t wave_sum_x_i32(int32_t v)
+{
+    v += (int32_t)lane_xor32<32>((uint32_t)v);
+    v += (int32_t)lane_xor32<16>((uint32_t)v);
+    v += (int32_t)lane_xor32<8>((uint32_t)v);
+    v += (int32_t)lane_xor32<4>((uint32_t)v);
+    v += (int32_t)lane_xor32<2>((uint32_t)v);
+    v += (int32_t)lane_xor32<1>((uint32_t)v);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_x_i64(int64_t v)
+{
+    v += (int64_t)lane_xor64<32>((uint64_t)v);
+    v += (int64_t)lane_xor64<16>((uint64_t)v);
+    v += (int64_t)lane_xor64<8>((uint64_t)v);
+    v += (int64_t)lane_xor64<4>((uint64_t)v);
+    v += (int64_t)lane_xor64<2>((uint64_t)v);
+    v += (int64_t)lane_xor64<1>((uint64_t)v);
+    return v;
+}
+
 // ---------------------------------------------------------------- refresh (A2, A4, A5)
 
 // Trace record of iteration t; cur/best as they stand after it.
@@ -572,8 +697,8 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             if (TY) s_rot[k] = gptr(d.open_rot)[k];
         }
         // barriers: s_open complete too
-        best = d.mode >= 2 ? block_best<kBlock, true>(best, s_red)
-                           : block_best<kBlock, false>(best, s_red);
+        best = d.mode >= 2 ? block_best_x<kBlock, true>(best, s_red)
+                           : block_best_x<kBlock, false>(best, s_red);
         // (permuted searches at the end of a pass keep going: every workgroup
         // recomputes the unchanged placement's state, and the leader either
         // starts the next pass or stops; nothing here reads what it writes)
@@ -768,8 +893,8 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             d.b2[m] = INT32_MIN;
             d.o1[m] = 0;
         }
-        const int32_t wc = wave_sum_i32(g1c);
-        const int64_t wd = wave_sum_i64((int64_t)g1d);
+        const int32_t wc = wave_sum_x_i32(g1c);
+        const int64_t wd = wave_sum_x_i64((int64_t)g1d);
         if (lane == 0) {
             atomicAdd(&s_cov[0], (u64)(int64_t)wc);
             atomicAdd(&s_dist[0], (u64)wd);
@@ -1448,59 +1573,6 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
 // more per list) instead of every closed row.  The terms added are exactly the
 // dense sweep's (the same integer arithmetic on the same elements), so the
 // scores are identical.
-
-// The value of lane (lane ^ J) of a full wave.  J = 1, 2 and 8 stay in the
-// vector ALU (DPP quad permutes and a rotate by 8 within each 16-lane row);
-// the other distances go through the LDS crossbar.  Every lane must be
-// active.
-template <int J>
-__device__ __forceinline__ uint64_t lane_xor64(uint64_t v)
-{
-    if constexpr (J == 1 || J == 2 || J == 8) {
-        constexpr int kCtrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
-        const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)v, kCtrl, 0xF, 0xF, false);
-        const int32_t hi =
-            __builtin_amdgcn_update_dpp(0, (int32_t)(v >> 32), kCtrl, 0xF, 0xF, false);
-        return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-    } else {
-        return __shfl_xor(v, J, 64);
-    }
-}
-
-template <int J>
-__device__ __forceinline__ uint32_t lane_xor32(uint32_t v)
-{
-    if constexpr (J == 1 || J == 2 || J == 8) {
-        constexpr int kCtrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x128);
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, kCtrl, 0xF, 0xF, false);
-    } else {
-        return (uint32_t)__shfl_xor((int32_t)v, J, 64);
-    }
-}
-
-__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int j)
-{
-    switch (j) {   // (j is a constant once the sorting network is unrolled)
-    case 1: return lane_xor32<1>(v);
-    case 2: return lane_xor32<2>(v);
-    case 4: return lane_xor32<4>(v);
-    case 8: return lane_xor32<8>(v);
-    case 16: return lane_xor32<16>(v);
-    default: return lane_xor32<32>(v);
-    }
-}
-
-__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int j)
-{
-    switch (j) {   // (j is a constant once the sorting network is unrolled)
-    case 1: return lane_xor64<1>(v);
-    case 2: return lane_xor64<2>(v);
-    case 4: return lane_xor64<4>(v);
-    case 8: return lane_xor64<8>(v);
-    case 16: return lane_xor64<16>(v);
-    default: return lane_xor64<32>(v);
-    }
-}
 
 // Sorted lists of one block x 64 missions: the C tile is staged in LDS, each
 // wave sorts a mission's 64 (cost, local id) keys across its lanes (bitonic,
