@@ -87,7 +87,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the instance-level sharding design is described in DESIGN.md)", file=sys.stderr)
+              "(more GPUs would each take a share of the instances, one process per GPU)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
