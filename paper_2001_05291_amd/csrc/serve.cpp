@@ -131,6 +131,8 @@ struct Server {
     bool stage_used[2] = {false, false};
     int round = 0;
     bool tiles_dirty = true;
+    int64_t retired_ok = 0;
+    int64_t fail_nth = 0;             // FS_SERVE_FAIL_NTH (tests): see retire()
     EngineTables tabs;
     EngineConfig ecfg;
 
@@ -161,6 +163,7 @@ fs_status Server::init()
 {
     FS_HIP(hipSetDevice(cfg.device));
     FS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    fail_nth = env_int("FS_SERVE_FAIL_NTH", 0);
     slots.assign(cfg.max_slots, Slot{});
     for (Slot &sl : slots) {
         FS_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
@@ -424,9 +427,15 @@ void Server::retire(int i, fs_status st, const char *msg)
     Instance &I = *sl.inst;
     Request *r = sl.req;
     std::vector<int32_t> best;
+    // (host-side fault injection for tests of this path: the n-th request
+    // retired with FS_OK is reported as failing the device-side check)
+    if (st == FS_OK && ++retired_ok == fail_nth && *sl.h_err == 0) *sl.h_err = -1;
     if (st == FS_OK) {
         best.assign(sl.h_best, sl.h_best + I.K);
-        I.last_best = best;
+        // only a consistent result seeds the instance's next warm start; after
+        // a failed one the next request starts from the last good placement
+        // (or the base ranking if there is none)
+        if (*sl.h_err == 0) I.last_best = best;
     }
     (void)hipFreeAsync(sl.ws, s);
     used -= (int64_t)sl.ws_bytes;
@@ -445,8 +454,10 @@ void Server::retire(int i, fs_status st, const char *msg)
             r->best = std::move(best);
             if (*sl.h_err) {
                 r->status = FS_E_INTERNAL;
-                r->err = "refreshed placement value disagrees with the move score at iteration " +
-                         std::to_string(*sl.h_err);
+                r->err = *sl.h_err > 0
+                             ? "refreshed placement value disagrees with the move score at "
+                               "iteration " + std::to_string(*sl.h_err)
+                             : std::string("consistency failure injected by FS_SERVE_FAIL_NTH");
             }
         } else {
             r->err = msg ? msg : "request failed";

@@ -3,6 +3,8 @@
     python -m paper_2001_05291_amd.profiling trace DB OUT.md --title T --command CMD
     python -m paper_2001_05291_amd.profiling traffic --fetch DB --write DB --kernel RE
         --copy RE --copy-bytes N --algorithmic-bytes N OUT.md --command CMD...
+    python -m paper_2001_05291_amd.profiling valu --db DB --kernel RE --workload W OUT.md
+        --command CMD
 
 ``trace`` writes per-kernel launch statistics (calls, mean / min / max
 duration).  ``traffic`` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per
@@ -129,6 +131,47 @@ def write_traffic(fetch_db: str, write_db: str, kernel_re: str, copy_re: str, co
     return total
 
 
+def write_valu(db: str, kernel_re: str, out: str, commands, workload: str):
+    """VALU work of one kernel from an SQ_INSTS_VALU counter run: wave-level
+    VALU instructions per dispatch (summed over the counter's instances),
+    times 64 lanes, as lane-operations per launch."""
+    v, n = counter_per_dispatch(db, kernel_re, "SQ_INSTS_VALU", most_used=True)
+    used = kernel_name(db, kernel_re, "SQ_INSTS_VALU")
+    extra = []
+    for ctr in ("SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES"):
+        try:
+            x, _ = counter_per_dispatch(db, kernel_re, ctr, most_used=True)
+            extra.append(f"- {ctr} per dispatch: {x:.0f}")
+        except SystemExit:
+            pass
+    lines = [f"# VALU work of `{kernel_re}` ({workload})", "",
+             "Command:", "", "```", *commands, "```", "",
+             f"- kernel measured: `{used}` (the most-dispatched match)",
+             f"- SQ_INSTS_VALU per dispatch: {v:.0f} wave instructions over {n} dispatches",
+             *extra,
+             f"- lane-operations per launch (x 64 lanes): {64 * v:.0f}", "",
+             f"workload: {workload}",
+             f"valu_lane_ops_per_launch: {64 * v:.0f}",
+             f"source_sha256: {source_hash()}"]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return 64 * v
+
+
+def read_valu(path: str, workload: str):
+    """VALU lane-operations per launch recorded in a summary, or None when it
+    is missing, for another workload, or taken with a different kernel
+    source."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(\w+): (.+)$", text, re.M))
+    if kv.get("workload") != workload or kv.get("source_sha256") != source_hash():
+        return None
+    return float(kv["valu_lane_ops_per_launch"])
+
+
 def sparse_sweep_bytes(C, open_ids, width: int = 64) -> int:
     """Bytes the sparse sweep needs in one iteration at placement open_ids:
     for every block of `width` base ids and every mission, the block's sorted
@@ -185,9 +228,17 @@ def main():
     r.add_argument("--algorithmic-bytes", type=int, required=True)
     r.add_argument("--workload", required=True)
     r.add_argument("--command", action="append", default=[])
+    v = sub.add_parser("valu")
+    v.add_argument("out")
+    v.add_argument("--db", required=True)
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--workload", required=True)
+    v.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
     if a.cmd == "trace":
         write_trace(a.db, a.out, a.title, a.command, a.copy, a.copy_bytes)
+    elif a.cmd == "valu":
+        write_valu(a.db, a.kernel, a.out, a.command, a.workload)
     else:
         write_traffic(a.fetch, a.write, a.kernel, a.copy, a.copy_bytes, a.algorithmic_bytes,
                       a.out, a.command, a.workload)

@@ -11,7 +11,9 @@ request streams are played through
           batched iteration.
 
 Each stream is played at saturation (every request at time 0) and as Poisson
-arrivals at fractions of the plain path's saturation rate.  Latency runs from
+arrivals at fractions of the plain path's saturation rate; the saturation
+stream is played once more on a server whose HBM budget (1 GiB) forces it to
+evict and rebuild tables.  Latency runs from
 a request's arrival to its result.  Every served result is compared with the
 plain result of the same request, which must be identical.
 """
@@ -137,8 +139,8 @@ def _mismatches(a, b):
     return bad
 
 
-def run(fs, torch, n_small=1024, n_large=64, n_requests=600, fractions=(0.5, 0.8, 1.0),
-        slots=128, budget=200 << 30, log=print):
+def run(fs, torch, n_small=4096, n_large=256, n_requests=600, fractions=(0.5, 0.8, 1.0),
+        slots=128, budget=200 << 30, evict_budget=1 << 30, log=print):
     cfg = synth.SERVE
     T, N, seed = cfg["T"], cfg["N"], cfg["seed"]
     log(f"[serve] pool: {n_small} small + {n_large} large instances")
@@ -192,6 +194,26 @@ def run(fs, torch, n_small=1024, n_large=64, n_requests=600, fractions=(0.5, 0.8
                 f"p50 {sm['p50_ms']:.2f} ms, p99 {sm['p99_ms']:.2f} ms")
     finally:
         stats = served.close()
+
+    # the saturation stream again on a fresh server under a 1 GB budget: about
+    # two large tables fit, so admissions evict idle tables (least recently
+    # used first) and rebuild them on their next request
+    evict = None
+    if evict_budget:
+        log(f"[serve] server under a {evict_budget / 2 ** 30:g} GiB budget: warming the pool")
+        small = ServedPath(fs, pool, T, N, slots, evict_budget)
+        try:
+            out, sm = small.play(streams[0], arrivals[0])
+        finally:
+            est = small.close()
+        ebad = _mismatches(out, plain_res[0])
+        evict = {"budget_gb": evict_budget / 2 ** 30, "stream": legs[0][0], **sm,
+                 "identical": ebad == 0, "mismatched_requests": ebad,
+                 "server_stats": {k: est[k] for k in ("evictions", "rebuilds", "steps",
+                                                      "completed")}}
+        log(f"[serve] served {legs[0][0]} under the small budget: {sm['solves_per_s']:.1f} "
+            f"solves/s, {est['evictions']} evictions, {ebad} mismatches")
+        bad += ebad
     return {
         "pool": {"small": n_small, "large": n_large, "table_gb": resident / 1e9},
         "requests_per_stream": n_requests, "T": T, "N": N, "slots": slots,
@@ -200,4 +222,5 @@ def run(fs, torch, n_small=1024, n_large=64, n_requests=600, fractions=(0.5, 0.8
         "plain": plain_sum, "served": served_sum,
         "identical": bad == 0, "mismatched_requests": bad,
         "server_stats": {k: stats[k] for k in ("evictions", "rebuilds", "steps", "completed")},
+        "eviction": evict,
     }

@@ -1,7 +1,7 @@
 """GPU tests of the repositioning server: every request's result equals the
 plain path (one tabu_solve per request, replayed in order with the same
 redraws and warm starts), whatever the number of slots and with evictions;
-and one request against the CPU oracle."""
+and chains of warm-started requests against the CPU oracle."""
 
 import numpy as np
 import pytest
@@ -127,20 +127,113 @@ def test_zero_iteration_request_and_no_redraw(fs):
     assert_same(served, plain)
 
 
-def test_first_request_against_oracle(fs):
-    insts, reqs = make_workload(1, 1, seed=5)
-    w, r = insts[0], reqs[0]
+def explain_mismatches(Cg, Co, Cfo):
+    """Each int32 entry where the GPU table differs from the oracle's is one
+    metre apart with the FP64 sum on a .5 rounding boundary (both roundings
+    are correct there)."""
+    for b, m in zip(*np.nonzero(Cg != Co)):
+        assert abs(int(Cg[b, m]) - int(Co[b, m])) == 1
+        assert abs(Cfo[b, m] - np.floor(Cfo[b, m]) - 0.5) <= 1e-12 * Cfo[b, m] + 1e-9
+
+
+def oracle_chain(fs, w, reqs, T, N):
+    """The requests of one instance replayed through the oracle in order:
+    redrawn mission coordinates, the cost table, and the oracle's Tabu
+    search warm-started from the previous request's best placement (the
+    base ranking for the first).  The search runs on the GPU-built table,
+    the shared input of the server and the oracle, after checking it against
+    the oracle's own table."""
+    inst = w["inst"]
+    coords = inst.missions.copy()
+    prev = None
+    out = []
+    for r in reqs:
+        coords[r["ids"]] = r["pd"]
+        Cg, Cfg = fs.build_cost_table(to_dev(inst.bases), to_dev(coords), want_cf=True)
+        Cg = Cg.cpu().numpy()
+        Cfg = Cfg.cpu().numpy()
+        Co, Cfo = oracle.cost_table(inst.bases, coords)
+        assert (np.abs(Cfg - Cfo) / Cfo).max() <= 1e-12
+        explain_mismatches(Cg, Co, Cfo)
+        o = oracle.tabu(Cg, w["K"], w["R"], T, N, init_open=prev)
+        prev = o.best_open
+        out.append(o)
+    return out
+
+
+def chain_workload(inst, K, R, n_req, seed):
+    w = dict(inst=inst, K=K, R=R)
+    reqs = []
+    for q in range(n_req):
+        ids, pairs = synth.perturbation(seed, inst.hospitals.shape[0], inst.M, 0.1, request=q)
+        reqs.append(dict(inst=0, ids=ids, pd=synth.missions_from_pairs(inst.hospitals, pairs)))
+    return w, reqs
+
+
+def assert_chain(served, chain):
+    for k, (s, o) in enumerate(zip(served, chain)):
+        assert np.array_equal(s.best_open, o.best_open), k
+        assert (s.coverage, s.distance, s.best_iter) == (o.coverage, o.distance, o.best_iter), k
+
+
+def test_warm_start_chain_against_oracle(fs):
+    """Five consecutive requests on one instance (each redraws 10% of the
+    missions and warm-starts from the previous best) equal the oracle's
+    chain, one request at a time and mixed with another instance's."""
+    inst = synth.make_instance(seed=55, B=150, H=450, M=2400)
+    w, reqs = chain_workload(inst, 11, 1_100_000, 5, seed=77)
+    chain = oracle_chain(fs, w, reqs, T=10, N=100)
+    served, _ = serve_all(fs, [w], reqs, T=10, N=100, max_slots=1)
+    assert_chain(served, chain)
+    # the same chain interleaved with requests on a second instance
+    other = synth.make_instance(seed=56, B=90, H=270, M=3100)
+    w2, reqs2 = chain_workload(other, 7, 1_000_000, 5, seed=78)
+    for r in reqs2:
+        r["inst"] = 1
+    mixed = [x for pair in zip(reqs, reqs2) for x in pair]
+    served, _ = serve_all(fs, [w, w2], mixed, T=10, N=100, max_slots=4)
+    assert_chain(served[0::2], chain)
+    assert_chain(served[1::2], oracle_chain(fs, w2, reqs2, T=10, N=100))
+
+
+@pytest.mark.timeout(900)
+def test_large_request_chain_against_oracle(fs):
+    """Two consecutive requests on a large resident instance (2,000 bases,
+    6,000 hospitals, 50,000 missions, 48 vehicles, 100 iterations, tenure
+    10) equal the oracle's warm-started chain."""
+    s = synth.SERVE_LARGE
+    inst = synth.make_instance(seed=100_000, B=s["B"], H=s["H"], M=s["M"])
+    w, reqs = chain_workload(inst, s["K"], 1_050_000, 2, seed=79)
+    chain = oracle_chain(fs, w, reqs, T=synth.SERVE["T"], N=synth.SERVE["N"])
+    served, _ = serve_all(fs, [w], reqs, T=synth.SERVE["T"], N=synth.SERVE["N"], max_slots=4)
+    assert_chain(served, chain)
+
+
+def test_failed_request_does_not_seed_warm_start(fs, monkeypatch):
+    """A request reported as inconsistent (the device-side check, injected
+    from the host here for the second request retired) fails with
+    FS_E_INTERNAL; its redraw stays applied, but the next request on the
+    instance warm-starts from the last consistent placement."""
+    monkeypatch.setenv("FS_SERVE_FAIL_NTH", "2")
+    insts, reqs = make_workload(1, 3, seed=11)
+    w = insts[0]
+    with fs.Server(max_slots=1) as sv:
+        iid = sv.register(w["inst"].bases, w["inst"].missions, w["K"], w["R"])
+        tickets = [sv.submit(iid, r["ids"], r["pd"], 5, 30) for r in reqs]
+        first = sv.wait(tickets[0])
+        with pytest.raises(fs.FleetstageError) as e:
+            sv.wait(tickets[1])
+        assert e.value.status == fs.FS_E_INTERNAL
+        third = sv.wait(tickets[2])
     coords = w["inst"].missions.copy()
-    coords[r["ids"]] = r["pd"]
-    Co, _ = oracle.cost_table(w["inst"].bases, coords, want_cf=False)
-    Cg, _ = fs.build_cost_table(to_dev(w["inst"].bases), to_dev(coords))
-    if not np.array_equal(Cg[:, : w["inst"].M].cpu().numpy(), Co):
-        pytest.skip("GPU and CPU tables differ at a rounding boundary for this draw")
-    o = oracle.tabu(Co, w["K"], w["R"], 5, 30)
-    served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=2)
-    assert np.array_equal(served[0].best_open, o.best_open)
-    assert (served[0].coverage, served[0].distance, served[0].best_iter) == (
-        o.coverage, o.distance, o.best_iter)
+    for r in reqs:
+        coords[r["ids"]] = r["pd"]
+    C, _ = fs.build_cost_table(to_dev(w["inst"].bases), to_dev(coords))
+    plain = fs.tabu_solve(C, w["K"], w["R"], 5, 30, init_open=torch.from_numpy(first.best_open),
+                          M=w["inst"].M, want_trace=False, want_assign=False)
+    assert np.array_equal(third.best_open, plain.best_open.cpu().numpy())
+    assert (third.coverage, third.distance, third.best_iter) == (
+        plain.coverage, plain.distance, plain.best_iter)
 
 
 def test_server_errors(fs):
