@@ -191,6 +191,30 @@ fs_status fs_tabu_solve(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int
                         int32_t *best_open_out, fs_score *score_out,
                         int32_t *assign_out, fs_trace_rec *trace_out, void *stream);
 
+/* fs_tabu_solve for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, outputs, results and errors as fs_tabu_solve; the caller
+ * still owns and passes every input and output buffer.  Every other device
+ * buffer the solve uses is carved from a static device array of the library
+ * (fs_noalloc_scratch_bytes(), 32 MiB), one per GPU, held until the process
+ * ends; no hipMalloc, hipFree or allocating routine is called.
+ *   - The stream must belong to the calling thread's current device.
+ *   - The dense sweep and the rule-chosen sweep variant are used (no sorted
+ *     lists, no autotuning); kernel timing is off during the call.
+ *   - All calls on one GPU share its array, which keeps the last call's
+ *     contents: calls that overlap on one GPU race, callers serialise them.
+ * Errors: those of fs_tabu_solve; FS_E_INVALID, before anything is launched,
+ * when the instance needs more workspace than the array holds (about
+ * 12 bytes per mission plus a few hundred bytes per base: M up to about two
+ * million at a few thousand bases).  Synchronises the stream before
+ * returning. */
+fs_status fs_tabu_solve_noalloc(const int32_t *C, int64_t ldc, int32_t B, int32_t M,
+                                int32_t K, const fs_params *p, const int32_t *init_open,
+                                int32_t *best_open_out, fs_score *score_out,
+                                int32_t *assign_out, fs_trace_rec *trace_out, void *stream);
+/* Size in bytes of the static device array fs_tabu_solve_noalloc works in. */
+int64_t fs_noalloc_scratch_bytes(void);
+
 /* Exact optimum of a small instance by enumeration: the stand-in for the
  * exact solver the paper's evaluation compares against (Section 5, Table 1).
  * Every K-subset of the B bases is scored (nearest open base per mission,

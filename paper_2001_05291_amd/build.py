@@ -37,7 +37,7 @@ EXTRA = {
     "cost_table.hip": ["-ffp-contract=off"],
 }
 SOURCES = ["common.cpp", "timing.cpp", "cost_table.hip", "rank.hip", "engine.hip",
-           "launchset.hip", "tabu.hip", "brute.hip", "fleet.cpp", "batch.cpp", "serve.cpp"]
+           "launchset.hip", "tabu.hip", "noalloc.hip", "brute.hip", "fleet.cpp", "batch.cpp", "serve.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

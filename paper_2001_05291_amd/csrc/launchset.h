@@ -29,8 +29,20 @@ struct InstSpec {
     int32_t *best_rot_out = nullptr;     // device K, or NULL
 };
 
+// Device memory a launch set is carved from instead of allocating its own
+// (the entry point that allocates nothing): p, cap bytes, 256-byte aligned.
+// A launch set built in it uses the dense sweep (the sparse sweep's sorted
+// lists are far larger) and the rule-chosen sweep variant (no autotuning,
+// which creates events).
+struct Workspace {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
 struct LaunchSet {
     void *dev = nullptr;
+    bool owned = true;               // dev was allocated here (freed on destruction)
+    bool tune = true;                // the autotuner may time sweep variants
     hipStream_t s = nullptr;
     EngineTables tabs;
     EngineConfig cfg;
@@ -50,8 +62,13 @@ struct LaunchSet {
 
 // Validates nothing (callers do); plans, allocates (stream-ordered) and
 // uploads.  target_wg: sweep workgroups wanted per instance (mission splits).
+// ws: carve the launch set from this workspace instead of allocating
+// (FS_E_INVALID when it does not fit).  need: when not NULL, only plan and
+// store the device bytes the launch set takes (nothing is allocated,
+// uploaded or launched).
 fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, LaunchSet &ls,
-                           hipStream_t s);
+                           hipStream_t s, const Workspace *ws = nullptr,
+                           size_t *need = nullptr);
 
 // Picks the fastest plan-preserving sweep variant for this launch set's shape
 // (cached per shape; skipped when the sweep variant is fixed by environment).
@@ -61,6 +78,14 @@ fs_status tune_sweep(LaunchSet &ls, hipStream_t s);
 // Reset, ranking, initial state, then N iterations (each: sweep, then
 // refresh, which applies the chosen move and recomputes the state).
 fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s);
+
+// The single-instance solve behind fs_tabu_solve (ws NULL: device buffers
+// allocated stream-ordered) and fs_tabu_solve_noalloc (every device buffer
+// carved from ws; FS_E_INVALID before any launch when it does not fit).
+fs_status tabu_solve_impl(const int32_t *C, int64_t ldc, int32_t B, int32_t M, int32_t K,
+                          const fs_params *p, const int32_t *init_open, int32_t *best_open_out,
+                          fs_score *score_out, int32_t *assign_out, fs_trace_rec *trace_out,
+                          hipStream_t s, const Workspace *ws);
 
 // Outputs kernel, then scores and error iterations to the host (synchronises).
 fs_status collect_results(LaunchSet &ls, std::vector<fs_score> &scores,

@@ -14,7 +14,7 @@ namespace fs {
 
 LaunchSet::~LaunchSet()
 {
-    if (dev) (void)hipFreeAsync(dev, s);
+    if (dev && owned) (void)hipFreeAsync(dev, s);
 }
 
 namespace {
@@ -22,7 +22,7 @@ size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 }  // namespace
 
 fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, LaunchSet &ls,
-                           hipStream_t s)
+                           hipStream_t s, const Workspace *ws, size_t *need)
 {
     const int n = (int)specs.size();
     if (n < 1) return fail(FS_E_INVALID, "empty launch set");
@@ -67,7 +67,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     const bool sparse_ok = n == 1 && !cfg.typed && specs[0].K <= kSparseMaxK &&
                            specs[0].B > specs[0].K;
     const bool sparse_pays = sparse_ok && specs[0].B - specs[0].K >= 2048 && specs[0].N >= 100;
-    cfg.sparse = sparse_ok && env_int("FS_SPARSE", sparse_pays ? 1 : 0) != 0;
+    cfg.sparse = sparse_ok && !ws && env_int("FS_SPARSE", sparse_pays ? 1 : 0) != 0;
 
     std::vector<InstPlan> plans(n);
     std::vector<int32_t> Mp(n);
@@ -121,7 +121,20 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
         total += instance_bytes(specs[i].B, specs[i].M, specs[i].K, plans[i]);
         if (!specs[i].init_host) total += a256(8 * (size_t)specs[i].B);
     }
-    FS_HIP(hipMallocAsync(&ls.dev, total, s));
+    if (need) {
+        *need = total;
+        return FS_OK;
+    }
+    if (ws) {
+        if (total > ws->cap)
+            return fail(FS_E_INVALID, "the solve needs %zu bytes of workspace, more than the "
+                                      "%zu bytes available", total, ws->cap);
+        ls.dev = ws->p;
+        ls.owned = false;
+        ls.tune = false;
+    } else {
+        FS_HIP(hipMallocAsync(&ls.dev, total, s));
+    }
     char *base = (char *)ls.dev;
 
     std::vector<char> head(o_ws, 0);
@@ -238,7 +251,7 @@ bool user_fixed_sweep()
 // The fastest is kept for this shape for the rest of the process.
 fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
 {
-    if (!ls.cfg.vec4 || ls.cfg.sparse || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
+    if (!ls.tune || !ls.cfg.vec4 || ls.cfg.sparse || ls.tabs.nsweep == 0 || user_fixed_sweep() ||
         env_int("FS_AUTOTUNE", 1) == 0)
         return FS_OK;
     TuneKey key{ls.tabs.ninst, ls.tabs.nsweep, ls.tabs.nscore, 0, 0,

@@ -108,6 +108,10 @@ def lib():
     L.fs_tabu_solve.restype = i32
     L.fs_tabu_solve.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(Params), vp, vp,
                                 ctypes.POINTER(Score), vp, vp, vp]
+    L.fs_tabu_solve_noalloc.restype = i32
+    L.fs_tabu_solve_noalloc.argtypes = L.fs_tabu_solve.argtypes
+    L.fs_noalloc_scratch_bytes.restype = i64
+    L.fs_noalloc_scratch_bytes.argtypes = []
     L.fs_brute_optimum.restype = i32
     L.fs_brute_optimum.argtypes = [vp, i64, i32, i32, i32, i32, vp, ctypes.POINTER(Score),
                                    ctypes.POINTER(i64), vp]
@@ -265,9 +269,8 @@ class SolveResult:
     trace: np.ndarray | None         # host structured array (TRACE_DTYPE)
 
 
-def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int = 0,
-               init_open=None, M: int | None = None, want_assign: bool = True,
-               want_trace: bool = True, stream=None, seed: int = 0) -> SolveResult:
+def _tabu_solve(entry, C, K, range_m, tenure, iterations, mode, init_open, M, want_assign,
+                want_trace, stream, seed):
     B, M, ldc = _table(C, M)
     dev = C.device
     p = Params(int(tenure), int(iterations), int(range_m), int(mode), int(seed) % 2**64)
@@ -280,13 +283,33 @@ def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int 
     if init_open is not None:
         init = init_open.to(device=dev, dtype=torch.int32).contiguous()
     sc = Score()
-    _check(lib().fs_tabu_solve(_table_ptr(C), ldc, B, M, int(K), ctypes.byref(p), _ptr(init),
-                               _ptr(best), ctypes.byref(sc), _ptr(assign),
-                               _ptr(trace) if n > 0 else None, _stream(stream)))
+    _check(entry(_table_ptr(C), ldc, B, M, int(K), ctypes.byref(p), _ptr(init),
+                 _ptr(best), ctypes.byref(sc), _ptr(assign),
+                 _ptr(trace) if n > 0 else None, _stream(stream)))
     tr = None
     if want_trace:
         tr = trace[: n * TRACE_DTYPE.itemsize].cpu().numpy().view(TRACE_DTYPE)
     return SolveResult(best, int(sc.coverage), int(sc.distance), int(sc.best_iter), assign, tr)
+
+
+def tabu_solve(C, K: int, range_m: int, tenure: int, iterations: int, mode: int = 0,
+               init_open=None, M: int | None = None, want_assign: bool = True,
+               want_trace: bool = True, stream=None, seed: int = 0) -> SolveResult:
+    return _tabu_solve(lib().fs_tabu_solve, C, K, range_m, tenure, iterations, mode, init_open,
+                       M, want_assign, want_trace, stream, seed)
+
+
+def tabu_solve_noalloc(C, K: int, range_m: int, tenure: int, iterations: int, mode: int = 0,
+                       init_open=None, M: int | None = None, want_assign: bool = True,
+                       want_trace: bool = True, stream=None, seed: int = 0) -> SolveResult:
+    """fs_tabu_solve_noalloc: the solve in the library's static device
+    workspace (the output tensors are allocated here, by the caller side)."""
+    return _tabu_solve(lib().fs_tabu_solve_noalloc, C, K, range_m, tenure, iterations, mode,
+                       init_open, M, want_assign, want_trace, stream, seed)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().fs_noalloc_scratch_bytes())
 
 
 def tabu_solve_batch(instances, tenure: int, iterations: int, mode: int = 0,
