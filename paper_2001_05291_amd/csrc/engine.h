@@ -26,11 +26,16 @@ struct InstDesc {
     uint64_t seed;           // permuted searches (modes 2, 3): seed of the scan orders
     // sparse sweep (one instance, homogeneous, K <= kSparseW): row groups are
     // blocks of kSparseW base ids (ngroups = blocks, nsplit = mission chunks);
-    // lst_cost / lst_id hold, for each block and mission, the block's bases in
-    // ascending (cost, id) order, rank-major: [block][rank][Mp]
+    // for each block and mission, the block's bases in ascending (cost, id)
+    // order, twice: the first kSparseHead ranks rank-major in lst_cost /
+    // lst_id ([block][rank][Mp], read by every mission), and all kSparseW
+    // ranks mission-major in mm_cost / mm_id ([block][Mp][rank], read only by
+    // missions whose walk goes past the head)
     int32_t sparse;
     int32_t *lst_cost;
     unsigned char *lst_id;
+    int32_t *mm_cost;
+    unsigned char *mm_id;
     int32_t *base_slot;      // B: closed slot (>= 0) or -1 - open slot
     int32_t nclosed, chunk, nsplit, ngroups;
     int32_t active;          // 0: every kernel skips this instance
@@ -88,6 +93,7 @@ struct InstPlan {
 };
 
 constexpr int kSparseW = 64;   // bases per block of the sparse sweep (one wave)
+constexpr int kSparseHead = 4; // ranks of each sorted list also stored rank-major
 constexpr int kSparseMaxK = 64;
 // Plan of the sparse sweep: blocks of kSparseW bases x mission chunks.
 InstPlan plan_sparse(int32_t B, int32_t M, int32_t K, int target_wg);
@@ -108,6 +114,9 @@ struct EngineConfig {
     // open slots of 64 missions) or kBlock (one mission per thread, all slots;
     // for small K and many missions); the refresh tiles are built to match
     int refresh_mpt = kRefreshMissions;
+    // with refresh_mpt == kBlock: 1024-thread workgroups, four tiles of 64
+    // missions whose waves split the open slots (large K over many missions)
+    bool refresh_wide = false;
     int Kmax = 1;
     bool sparse = false;   // the sparse sweep (single homogeneous instance)
     // some instance has a typed fleet: the sweep keeps the rotary-only

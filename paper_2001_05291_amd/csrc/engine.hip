@@ -626,10 +626,15 @@ __device__ void write_record(const InstDesc &d, int32_t t, const SolveState &s, 
 // added with integer atomics into one of kStripes accumulator copies (exact in
 // any order).  TY: the launch set holds a typed fleet (vehicle types per slot,
 // rotary-only missions, base kinds travelling with the swapped bases).
-template <int MPT, bool TY>
-__global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__ descs,
-                                                    const Tile *__restrict__ tiles, int32_t step)
+template <int MPT, bool TY, int BS = kBlock>
+__global__ __launch_bounds__(BS) void k_refresh(const InstDesc *__restrict__ descs,
+                                                const Tile *__restrict__ tiles, int32_t step)
 {
+    // BS == kWideBlock: MPT = 256 missions as four tiles of 64, each with four
+    // waves splitting the open slots (a quarter of the workgroups of the
+    // 64-mission form, each reducing the candidates once for 256 missions)
+    static_assert(BS == kBlock || (BS == kWideBlock && MPT == 4 * kRefreshMissions),
+                  "refresh geometry");
     const Tile tl = group_tile(tiles);
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
@@ -644,9 +649,9 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     u64 *s_dist = s_cov + (K + 1);
     int32_t *s_open = reinterpret_cast<int32_t *>(s_dist + (K + 1));
     int32_t *s_rot = s_open + K;   // vehicle type per slot (never changes in a search)
-    __shared__ int32_t p_v1[kBlock / 64][64], p_i1[kBlock / 64][64], p_s1[kBlock / 64][64],
-        p_v2[kBlock / 64][64];
-    __shared__ Candidate s_red[kBlock / 64 + 1];
+    __shared__ int32_t p_v1[BS / 64][64], p_i1[BS / 64][64], p_s1[BS / 64][64],
+        p_v2[BS / 64][64];
+    __shared__ Candidate s_red[BS / 64 + 1];
     __shared__ int32_t s_improved;
 
     if (t >= 1) {
@@ -655,12 +660,12 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         // group and no move; the candidate array always holds one entry.)
         const int32_t ncand = d.ngroups;
         const int32_t stopped = gptr(st)->stopped;
-        constexpr int CU = 4;
+        constexpr int CU = BS == kBlock ? 4 : 1;
         const int32_t qlast = ncand > 0 ? ncand - 1 : 0;
         Candidate cq[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u)
-            cq[u] = gload(d.cand + min((int32_t)threadIdx.x + u * kBlock, qlast));
+            cq[u] = gload(d.cand + min((int32_t)threadIdx.x + u * BS, qlast));
         const int32_t k0 = (int32_t)threadIdx.x < K ? (int32_t)threadIdx.x : 0;
         const int32_t op0 = gptr(d.open)[k0];
         const int32_t or0 = TY ? gptr(d.open_rot)[k0] : 0;
@@ -679,12 +684,12 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         Candidate best = no_cand();
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
-            const bool in = (int32_t)threadIdx.x + u * kBlock < ncand;
+            const bool in = (int32_t)threadIdx.x + u * BS < ncand;
             if (in && (d.mode >= 2 ? cand_better<true>(cq[u], best)
                                    : cand_better<false>(cq[u], best)))
                 best = cq[u];
         }
-        for (int32_t q = threadIdx.x + CU * kBlock; q < ncand; q += kBlock) {
+        for (int32_t q = threadIdx.x + CU * BS; q < ncand; q += BS) {
             const Candidate c = gload(d.cand + q);
             if (d.mode >= 2 ? cand_better<true>(c, best) : cand_better<false>(c, best)) best = c;
         }
@@ -692,13 +697,13 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             s_open[threadIdx.x] = op0;
             if (TY) s_rot[threadIdx.x] = or0;
         }
-        for (int k = threadIdx.x + kBlock; k < K; k += kBlock) {
+        for (int k = threadIdx.x + BS; k < K; k += BS) {
             s_open[k] = gptr(d.open)[k];
             if (TY) s_rot[k] = gptr(d.open_rot)[k];
         }
         // barriers: s_open complete too
-        best = d.mode >= 2 ? block_best_x<kBlock, true>(best, s_red)
-                           : block_best_x<kBlock, false>(best, s_red);
+        best = d.mode >= 2 ? block_best_x<BS, true>(best, s_red)
+                           : block_best_x<BS, false>(best, s_red);
         // (permuted searches at the end of a pass keep going: every workgroup
         // recomputes the unchanged placement's state, and the leader either
         // starts the next pass or stops; nothing here reads what it writes)
@@ -760,19 +765,19 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
                 }
             }
             if (s_improved)
-                for (int k = threadIdx.x; k < K; k += kBlock)
+                for (int k = threadIdx.x; k < K; k += BS)
                     d.best_open[k] = (valid && k == i_slot) ? best.j_base : s_open[k];
         }
         __syncthreads();
         if (valid && threadIdx.x == 0) s_open[i_slot] = best.j_base;
     } else {
         const int32_t *first = d.open;
-        for (int k = threadIdx.x; k < K; k += kBlock) {
+        for (int k = threadIdx.x; k < K; k += BS) {
             s_open[k] = first[k];
             if (TY) s_rot[k] = d.open_rot[k];
         }
     }
-    for (int k = threadIdx.x; k <= K; k += kBlock) {
+    for (int k = threadIdx.x; k <= K; k += BS) {
         s_cov[k] = 0;
         s_dist[k] = 0;
     }
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     int32_t m, v1 = INT32_MAX, i1 = INT32_MAX, s1 = 0, v2 = INT32_MAX;
     bool owner;   // this thread holds mission m's final nearest / second-nearest
     int32_t kind; // 1: a rotary-only mission (only rotary-wing slots can fly it)
-    if constexpr (MPT == kBlock) {
+    if constexpr (MPT == kBlock && BS == kBlock) {
         // one mission per thread, every open slot in turn (small K)
         m = tl.g * MPT + threadIdx.x;
         owner = true;
@@ -816,13 +821,15 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
             }
         }
     } else {
-        m = tl.g * MPT + lane;
-        owner = wave == 0;
+        // four waves per 64 missions, splitting the open slots
+        constexpr int W = 4, UNR = 16;
+        const int sub = wave / W, ws = wave % W;
+        m = tl.g * MPT + sub * 64 + lane;
+        owner = ws == 0;
         kind = (TY && d.rho && m < M) ? (d.rho[m] != 0) : 0;
         if (m < M) {
             const int32_t *col = d.C + m;
-            constexpr int W = kBlock / 64, UNR = 16;
-            for (int32_t k0 = wave; k0 < K; k0 += W * UNR) {
+            for (int32_t k0 = ws; k0 < K; k0 += W * UNR) {
                 int32_t c[UNR], id[UNR];
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
@@ -853,13 +860,13 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
         p_s1[wave][lane] = s1;
         p_v2[wave][lane] = v2;
         __syncthreads();
-        if (wave == 0) {
-            v1 = p_v1[0][lane];
-            i1 = p_i1[0][lane];
-            s1 = p_s1[0][lane];
-            v2 = p_v2[0][lane];
+        if (ws == 0) {
+            v1 = p_v1[wave][lane];
+            i1 = p_i1[wave][lane];
+            s1 = p_s1[wave][lane];
+            v2 = p_v2[wave][lane];
 #pragma unroll
-            for (int w = 1; w < kBlock / 64; ++w) {
+            for (int w = wave + 1; w < wave + W; ++w) {
                 const int32_t bv1 = p_v1[w][lane], bi1 = p_i1[w][lane];
                 if (bv1 < v1 || (bv1 == v1 && bi1 < i1)) {
                     v2 = min(v1, p_v2[w][lane]);
@@ -902,7 +909,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh(const InstDesc *__restrict__
     }
     __syncthreads();
     Acc *acc = d.acc[(t + 1) & 1] + (blockIdx.x & (kStripes - 1)) * (K + 1);
-    for (int k = threadIdx.x; k <= K; k += kBlock) {
+    for (int k = threadIdx.x; k <= K; k += BS) {
         const u64 c = s_cov[k], dd = s_dist[k];
         if (c | dd) {
             atomicAdd(&acc[k].cov, c);
@@ -1677,15 +1684,15 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
         }
     }
     __syncthreads();
-    // four consecutive missions of one rank per thread and step: one 16-byte
-    // store of costs and one 4-byte store of ids (Mp is a multiple of 4, so a
-    // quad lies wholly inside or outside the padded mission range, and every
-    // quad's address is 16- and 4-byte aligned)
+    // The head ranks rank-major: four consecutive missions of one rank per
+    // thread, one 16-byte store of costs and one 4-byte store of ids (Mp is a
+    // multiple of 4, so a quad lies wholly inside or outside the padded
+    // mission range, and every quad's address is 16- and 4-byte aligned).
     const int64_t Mp = d.Mp;
-    for (int32_t u = threadIdx.x; u < kSparseW * 16; u += kBlock) {
+    for (int32_t u = threadIdx.x; u < kSparseHead * 16; u += kBlock) {
         const int32_t r = u >> 4, mm = (u & 15) * 4, m = mg * 64 + mm;
         if (m < Mp) {
-            const int64_t at = ((int64_t)q * kSparseW + r) * Mp + m;
+            const int64_t at = ((int64_t)q * kSparseHead + r) * Mp + m;
             v4i c;
             c[0] = s_cost[r][mm];
             c[1] = s_cost[r][mm + 1];
@@ -1694,6 +1701,32 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
             *reinterpret_cast<v4i *>(d.lst_cost + at) = c;
             *reinterpret_cast<uint32_t *>(d.lst_id + at) =
                 *reinterpret_cast<const uint32_t *>(&s_id[r][mm]);
+        }
+    }
+    // Every rank mission-major: sixteen consecutive ranks of one mission per
+    // thread, four 16-byte stores of costs and one of ids (a wave writes 4 KB
+    // of consecutive costs).
+    for (int32_t u = threadIdx.x; u < 64 * (kSparseW / 16); u += kBlock) {
+        const int32_t mm = u / (kSparseW / 16), r0 = (u % (kSparseW / 16)) * 16;
+        const int32_t m = mg * 64 + mm;
+        if (m < Mp) {
+            const int64_t at = ((int64_t)q * Mp + m) * kSparseW + r0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                v4i c;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) c[e] = s_cost[r0 + 4 * v + e][mm];
+                *reinterpret_cast<v4i *>(d.mm_cost + at + 4 * v) = c;
+            }
+            v4i ids;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w |= (uint32_t)s_id[r0 + 4 * v + e][mm] << (8 * e);
+                ids[v] = (int32_t)w;
+            }
+            *reinterpret_cast<v4i *>(d.mm_id + at) = ids;
         }
     }
 }
@@ -1756,13 +1789,36 @@ __device__ __forceinline__ void sparse_rows(const InstDesc &d, int32_t q, bool w
     if (lane == 0) *s_nrows = (int32_t)__builtin_popcountll(mask);
 }
 
-constexpr int kSparseRanks = 8;   // ranks loaded together per step of a walk
+// One element of a walk: the dense visit's terms while c < b2 and the base is
+// a closed row of the block; the first c >= b2 ends the walk (the list is
+// sorted, so no later element contributes).
+#define FS_SPARSE_STEP(c, id)                                                              \
+    do {                                                                                   \
+        if (act && (c) < b2) {                                                             \
+            const int32_t row = s_rowof[(id)];                                             \
+            if (row >= 0)                                                                  \
+                visit_sparse((c), b1, b2, o1, g1c, g1d, g2c, g2d, R, s_t1c + row,          \
+                             s_t1d + row, L.bc + row * K, L.bd + row * K);                 \
+        } else {                                                                           \
+            act = false;                                                                   \
+        }                                                                                  \
+    } while (0)
 
-// One workgroup = base block g x mission chunk sp.  Each wave takes 64
-// missions at a time and walks their lists kSparseRanks ranks per step while
-// any lane still has c < b2.
+constexpr int kSparseQ = 128;   // queued walks per wave: below 64 + 64 before a drain
+
+// One workgroup = base block g x mission chunk sp.  Each wave takes 256
+// missions at a time, four consecutive ones per lane (16-byte loads of the
+// state and of each head rank, all in flight together), and walks their
+// head ranks.  A mission still below b2 after the head is queued in LDS
+// (ballot + mbcnt; the queue length is wave-uniform); 64 queued walks at a
+// time then continue on the mission-major lists with every lane busy, each
+// lane gathering its mission's state and eight ranks of its list (32
+// contiguous bytes of costs, 8 of ids) in one round, and going on alone in
+// the rare case that it needs more.  A wave thus waits for one round of
+// loads per 256 missions plus one per 64 continued walks, instead of one
+// per rank batch of every group of 64 missions.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_sweep_sparse(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restrict__ descs,
                                                      const Tile *__restrict__ tiles, int32_t step)
 {
     const Tile tl = sweep_tile(descs, tiles);
@@ -1782,6 +1838,7 @@ __global__ __launch_bounds__(BS) void k_sweep_sparse(const InstDesc *__restrict_
     __shared__ u64 s_t1d[kSparseW];
     __shared__ int32_t s_nrows;
     __shared__ Candidate s_red[BS / 64 + 1];
+    __shared__ int32_t s_q[BS / 64][kSparseQ];
 
     if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
     for (int q = threadIdx.x; q < kSparseW * K; q += BS) {
@@ -1797,43 +1854,102 @@ __global__ __launch_bounds__(BS) void k_sweep_sparse(const InstDesc *__restrict_
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t m0 = tl.sp * d.chunk, m1 = min(d.Mp, m0 + d.chunk);
     const int64_t Mp = d.Mp;
-    const int32_t *lc = d.lst_cost + (int64_t)tl.g * kSparseW * Mp;
-    const unsigned char *li = d.lst_id + (int64_t)tl.g * kSparseW * Mp;
-    for (int32_t mw = m0 + (int32_t)(threadIdx.x & ~63); mw < m1; mw += BS) {
-        const int32_t m = mw + lane;
-        const bool in = m < m1;
-        const int32_t b1 = in ? d.b1[m] : 0, b2 = in ? d.b2[m] : INT32_MIN,
-                      o1 = in ? d.o1[m] : 0;
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    typedef const __attribute__((address_space(1))) uint32_t gu32;
+    typedef const __attribute__((address_space(1))) uint64_t gu64;
+    const int32_t *hc = d.lst_cost + (int64_t)tl.g * kSparseHead * Mp;
+    const unsigned char *hi = d.lst_id + (int64_t)tl.g * kSparseHead * Mp;
+    const int32_t *tc = d.mm_cost + (int64_t)tl.g * Mp * kSparseW;
+    const unsigned char *ti = d.mm_id + (int64_t)tl.g * Mp * kSparseW;
+    int32_t *myq = s_q[wave];
+    int32_t qlen = 0;
+
+    // The continued walks of queue entries [0, n): one per lane, ranks from
+    // kSparseHead on.
+    auto drain = [&](int32_t n) {
+        __builtin_amdgcn_wave_barrier();
+        const bool have = lane < n;
+        const int32_t m = have ? myq[lane] : m0;
+        const gv4i *myc = (const gv4i *)(tc + (int64_t)m * kSparseW);
+        const gu64 *myi = (const gu64 *)(ti + (int64_t)m * kSparseW);
+        // the state and the first eight ranks go out together
+        const int32_t b1 = ((const gi32 *)d.b1)[m], b2 = ((const gi32 *)d.b2)[m],
+                      o1 = ((const gi32 *)d.o1)[m];
+        v4i c0 = myc[0], c1 = myc[1];
+        uint64_t ids = myi[0];
         const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
         const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
-        const int32_t mc = in ? m : m0;   // in-bounds address for idle lanes
-        // ranks in batches of kSparseRanks, every load of a batch in flight
-        // together; the wave stops at the first batch where no lane is below b2
-        bool act = in;
-        for (int32_t r0 = 0; r0 < kSparseW; r0 += kSparseRanks) {
-            if (__builtin_amdgcn_ballot_w64(act) == 0) break;
-            int32_t cs[kSparseRanks];
-            int32_t ids[kSparseRanks];
+        bool act = have;
+        for (int32_t r8 = 0; r8 < kSparseW / 8; ++r8) {
+            if (r8 > 0) {
+                if (__builtin_amdgcn_ballot_w64(act) == 0) break;
+                if (act) {
+                    c0 = myc[2 * r8];
+                    c1 = myc[2 * r8 + 1];
+                    ids = myi[r8];
+                }
+            }
+            int32_t cs[8];
 #pragma unroll
-            for (int r = 0; r < kSparseRanks; ++r) {
-                cs[r] = lc[(r0 + r) * Mp + mc];
-                ids[r] = li[(r0 + r) * Mp + mc];
+            for (int e = 0; e < 4; ++e) {
+                cs[e] = c0[e];
+                cs[4 + e] = c1[e];
             }
 #pragma unroll
-            for (int r = 0; r < kSparseRanks; ++r) {
-                if (act && cs[r] < b2) {
-                    const int32_t row = s_rowof[ids[r]];
-                    if (row >= 0)
-                        visit_sparse(cs[r], b1, b2, o1, g1c, g1d, g2c, g2d, R, s_t1c + row,
-                                     s_t1d + row, L.bc + row * K, L.bd + row * K);
-                } else {
-                    act = false;
-                }
+            for (int e = 0; e < 8; ++e) {
+                if (r8 == 0 && e < kSparseHead) continue;
+                FS_SPARSE_STEP(cs[e], (int32_t)((ids >> (8 * e)) & 0xFF));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    for (int32_t mw = m0 + wave * 256; mw < m1; mw += BS * 4) {
+        const int32_t mq = mw + 4 * lane;    // this lane's four missions mq .. mq + 3
+        const bool in = mq < m1;             // (Mp and the chunk are multiples of 4)
+        const int32_t mc = in ? mq : m0;     // in-bounds address for idle lanes
+        v4i hcs[kSparseHead];
+        uint32_t hid[kSparseHead];
+#pragma unroll
+        for (int r = 0; r < kSparseHead; ++r) {
+            hcs[r] = *(const gv4i *)(hc + r * Mp + mc);
+            hid[r] = *(const gu32 *)(hi + r * Mp + mc);
+        }
+        const v4i vb1 = *(const gv4i *)(d.b1 + mc), vb2 = *(const gv4i *)(d.b2 + mc),
+                  vo1 = *(const gv4i *)(d.o1 + mc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int32_t b1 = vb1[e], b2 = in ? vb2[e] : INT32_MIN, o1 = vo1[e];
+            const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
+            const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+            bool act = in;
+#pragma unroll
+            for (int r = 0; r < kSparseHead; ++r)
+                FS_SPARSE_STEP(hcs[r][e], (int32_t)((hid[r] >> (8 * e)) & 0xFF));
+            // walks that go on past the head join the queue
+            const u64 mask = __builtin_amdgcn_ballot_w64(act);
+            if (mask == 0) continue;
+            if (act) {
+                const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask,
+                                                                     (uint32_t)qlen));
+                myq[at] = mq + e;
+            }
+            qlen = __builtin_amdgcn_readfirstlane(qlen + (int32_t)__builtin_popcountll(mask));
+            if (qlen >= 64) {
+                drain(64);
+                qlen -= 64;
+                const int32_t rest = lane < qlen ? myq[64 + lane] : 0;
+                __builtin_amdgcn_wave_barrier();
+                if (lane < qlen) myq[lane] = rest;
+                __builtin_amdgcn_wave_barrier();
             }
         }
     }
+    if (qlen > 0) drain(qlen);
     __syncthreads();
     const int32_t nrows = s_nrows;
     if (scoring) {
@@ -1859,6 +1975,8 @@ __global__ __launch_bounds__(BS) void k_sweep_sparse(const InstDesc *__restrict_
         }
     }
 }
+
+#undef FS_SPARSE_STEP
 
 // Scores one base block from its sums over the mission chunks (added by the
 // sweep's chunks) and clears them for the next iteration (all kSparseW rows:
@@ -2183,8 +2301,10 @@ InstPlan plan_sparse(int32_t B, int32_t M, int32_t K, int target_wg)
     p.sparse = 1;
     p.nclosed = B - K;
     p.ngroups = (B + kSparseW - 1) / kSparseW;
-    // mission chunks of at least 1,024 missions, enough to fill the GPU
-    int nsplit = std::max(1, (std::max(target_wg, 1) + p.ngroups - 1) / p.ngroups);
+    // mission chunks of at least 1,024 missions; at most target_wg workgroups
+    // in all, so that the whole sweep is resident at once (a second, partial
+    // round of workgroups would run alone at the end)
+    int nsplit = std::max(1, std::max(target_wg, 1) / p.ngroups);
     nsplit = std::min(nsplit, std::max(1, Mp / 1024));
     nsplit = std::max(1, env_int("FS_SPARSE_SPLIT", nsplit));
     int chunk = (Mp + nsplit - 1) / nsplit;
@@ -2214,7 +2334,9 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
     n += 2 * align_up(4 * (size_t)K, 256);                      // best_open, best_sorted
     if (p.sparse) {
         const size_t lst = (size_t)p.ngroups * kSparseW * Mp;
-        n += align_up(4 * lst, 256) + align_up(lst, 256);   // sorted lists: costs, ids
+        const size_t head = (size_t)p.ngroups * kSparseHead * Mp;
+        n += align_up(4 * head, 256) + align_up(head, 256);   // sorted heads: costs, ids
+        n += align_up(4 * lst, 256) + align_up(lst, 256);     // sorted lists: costs, ids
         n += align_up(4 * (size_t)B, 256);                  // base_slot
         if (p.nsplit > 1) {   // the blocks' sums over mission chunks
             const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
@@ -2261,10 +2383,15 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.lst_cost = nullptr;
     d.lst_id = nullptr;
     d.base_slot = nullptr;
+    d.mm_cost = nullptr;
+    d.mm_id = nullptr;
     if (p.sparse) {
         const size_t lst = (size_t)p.ngroups * kSparseW * Mp;
-        d.lst_cost = (int32_t *)take(4 * lst);
-        d.lst_id = (unsigned char *)take(lst);
+        const size_t head = (size_t)p.ngroups * kSparseHead * Mp;
+        d.lst_cost = (int32_t *)take(4 * head);
+        d.lst_id = (unsigned char *)take(head);
+        d.mm_cost = (int32_t *)take(4 * lst);
+        d.mm_id = (unsigned char *)take(lst);
         d.base_slot = (int32_t *)take(4 * (size_t)B);
         if (p.nsplit > 1) {
             const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
@@ -2340,6 +2467,8 @@ typedef void (*RefreshKernel)(const InstDesc *, const Tile *, int32_t);
 
 RefreshKernel refresh_kernel(const EngineConfig &c)
 {
+    if (c.refresh_wide)
+        return c.typed ? k_refresh<kBlock, true, kWideBlock> : k_refresh<kBlock, false, kWideBlock>;
     if (c.refresh_mpt == kBlock)
         return c.typed ? k_refresh<kBlock, true> : k_refresh<kBlock, false>;
     return c.typed ? k_refresh<kRefreshMissions, true> : k_refresh<kRefreshMissions, false>;
@@ -2349,7 +2478,8 @@ RefreshKernel refresh_kernel(const EngineConfig &c)
 fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s)
 {
     if (t.nrefresh > 0) {
-        refresh_kernel(c)<<<t.nrefresh, kBlock, refresh_lds_bytes(c.Kmax), s>>>(
+        refresh_kernel(c)<<<t.nrefresh, c.refresh_wide ? kWideBlock : kBlock,
+                            refresh_lds_bytes(c.Kmax), s>>>(
             t.desc, t.single ? nullptr : t.refresh, step0);
         FS_HIP(hipGetLastError());
     }
@@ -2442,7 +2572,7 @@ fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t s
 {
     if (t.nrefresh == 0) return FS_OK;
     TimedLaunch timed(1);
-    launch_timed(refresh_kernel(c), dim3(t.nrefresh), dim3(kBlock),
+    launch_timed(refresh_kernel(c), dim3(t.nrefresh), dim3(c.refresh_wide ? kWideBlock : kBlock),
                  (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), t.desc,
                  t.single ? nullptr : t.refresh, step);
     FS_HIP(hipGetLastError());

@@ -85,6 +85,12 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     for (int i = 0; i < n; ++i) refresh64 += (Mp[i] + kRefreshMissions - 1) / kRefreshMissions;
     cfg.refresh_mpt = env_int("FS_REFRESH_WIDE", Kmax <= 32 && refresh64 >= 4096) != 0
                           ? kBlock : kRefreshMissions;
+    // larger K over many missions: 256 missions per 1024-thread workgroup
+    // (four waves per 64 missions splitting the slots), a quarter of the
+    // workgroups, each reducing the row-group candidates once
+    cfg.refresh_wide = cfg.refresh_mpt == kRefreshMissions &&
+                       env_int("FS_REFRESH_SPLIT4", refresh64 >= 1024) != 0;
+    if (cfg.refresh_wide) cfg.refresh_mpt = kBlock;
     build_tiles(plans, Mp, sweep, score, refresh, cfg.refresh_mpt);
     // few long row groups: 1024-thread workgroups keep four times as many
     // waves in flight, so each thread has fewer dependent load rounds

@@ -230,6 +230,17 @@ def test_tabu_full_trace_configs(cfg):
     assert_same_result(g, o, C, c["R"])
 
 
+@pytest.mark.parametrize("split4", [0, 1])
+def test_refresh_forms_medium(split4):
+    # the refresh in 64-mission workgroups and in 1024-thread workgroups of
+    # 256 missions (four waves per 64 missions splitting the open slots)
+    c = synth.WORKLOADS["medium"]
+    _, C = instance_and_table("medium")
+    with env(FS_REFRESH_SPLIT4=split4, FS_REFRESH_WIDE=0):
+        g, o = run_both(C, c["K"], c["R"], c["T"], 120)
+    assert_same_result(g, o, C, c["R"])
+
+
 @pytest.mark.parametrize("cfg", ["small", "medium"])
 def test_local_search_configs(cfg):
     c = synth.WORKLOADS[cfg]

@@ -1,6 +1,7 @@
 """Seeded random searches under random launch geometries: every combination
 of rows per workgroup, loads in flight, queued or in-place scoring,
-1024-thread workgroups, mission splits, refresh width, dense or sparse sweep
+1024-thread workgroups, mission splits, refresh width and slot split, dense or
+sparse sweep
 and the autotuner gives the oracle's trajectory bit for bit (modes 0-3,
 Section 4.3; random tables, ties, costs beyond 2^26), for single instances,
 ragged batches and typed fleets."""
@@ -20,7 +21,7 @@ from gpu_util import assert_trace_equal, padded_table  # noqa: E402
 fs = None
 
 KEYS = ("FS_SWEEP_J", "FS_SWEEP_U", "FS_SWEEP_QUEUE", "FS_SWEEP_WIDE", "FS_SWEEP_SPLIT",
-        "FS_REFRESH_WIDE", "FS_SPARSE", "FS_SPARSE_SPLIT", "FS_AUTOTUNE")
+        "FS_REFRESH_WIDE", "FS_REFRESH_SPLIT4", "FS_SPARSE", "FS_SPARSE_SPLIT", "FS_AUTOTUNE")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -53,6 +54,8 @@ def draw_env(rng):
         env["FS_SWEEP_SPLIT"] = int(rng.integers(1, 5))
     if rng.random() < 0.3:
         env["FS_REFRESH_WIDE"] = int(rng.integers(0, 2))
+    if rng.random() < 0.3:
+        env["FS_REFRESH_SPLIT4"] = int(rng.integers(0, 2))
     if rng.random() < 0.4:
         env["FS_SPARSE"] = int(rng.integers(0, 2))
     if rng.random() < 0.3:
