@@ -119,6 +119,11 @@ struct EngineConfig {
     bool refresh_wide = false;
     int Kmax = 1;
     bool sparse = false;   // the sparse sweep (single homogeneous instance)
+    // persistent search: one workgroup per instance runs all N iterations
+    // (k_solo); solo_lds is its dynamic LDS, sized for the largest instance
+    bool persistent = false;
+    bool solo_tab = false;     // the cost tables are staged in LDS too
+    uint32_t solo_lds = 0;
     // some instance has a typed fleet: the sweep keeps the rotary-only
     // missions' common term apart (queued or scalar variant, U = 1, 256
     // threads; other launch sets never pay for it)
@@ -139,6 +144,8 @@ struct EngineTables {
     int nscore = 0;
     const Tile *refresh = nullptr;
     int nrefresh = 0;
+    const Tile *solo = nullptr;    // persistent search: one tile per instance, largest first
+    int nsolo = 0;
     // one instance with the tiles of build_tiles (row group major, mission
     // chunk minor): the sweep, score and refresh kernels take their tile from
     // the block index instead of reading the table
@@ -191,6 +198,14 @@ fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t s
 // assignment into assign_out, and (score, error iteration) into device arrays.
 fs_status engine_outputs(const EngineTables &t, const EngineConfig &c, fs_score *scores,
                          int32_t *errors, hipStream_t s);
+// Persistent search: every remaining iteration of every instance in one
+// launch, one workgroup per instance (after engine_init).
+fs_status engine_persistent(const EngineTables &t, const EngineConfig &c, hipStream_t s);
+// LDS of the persistent search's workgroup for one instance.
+// (tab_B > 0: with the B x Mp table staged in LDS as well)
+size_t solo_lds_of(int32_t Mp, int32_t K, int32_t nclosed, int32_t tab_B = 0);
+constexpr int kSoloMaxMissions = 1 << 24;   // mission index and row in one queue word
+constexpr int kSoloMaxKPersist = 64;        // nearest slot kept in one byte
 fs_status engine_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 fs_status engine_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 

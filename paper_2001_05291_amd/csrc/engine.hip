@@ -2146,6 +2146,420 @@ __global__ __launch_bounds__(kBlock) void k_assign(const InstDesc *__restrict__ 
     d.assign_out[m] = v <= d.R ? who : -1;
 }
 
+// ---------------------------------------------------------------- persistent search (A6)
+//
+// One workgroup runs one instance's whole search: every iteration's sweep,
+// argmax, move and state refresh, with the per-mission state (b1, b2, o1),
+// the open and closed lists with their tabu expiries, and G / L_k resident in
+// LDS.  Workgroups never wait for one another, so a ragged batch of instances
+// is a single launch of the whole iteration loop (after the base ranking and
+// the initial state), and a small instance pays no launch per iteration.
+// The arithmetic is the multi-workgroup engine's: the same terms per element
+// (visit_hit), the same move order and admissibility, the same commit, so
+// the trajectory is identical.
+//
+// Sweep: each wave takes kSoloJ closed rows at a time and streams every
+// mission of them (16-byte row loads, b2 from LDS); elements below b2 are
+// queued per wave and scored 64 at a time into the wave's own bins; the wave
+// then scores its kSoloJ x K moves and keeps its best candidate.  Refresh:
+// one mission per thread over the K open rows (sixteen loads in flight).
+
+constexpr int kSoloWaves = 8;
+constexpr int kSoloBlock = 64 * kSoloWaves;
+constexpr int kSoloJ = 4;
+constexpr int kSoloU = 2;
+constexpr int kSoloQ = 128;
+
+struct SoloLayout {
+    uint32_t Ld, nLd, bd, b1, b2, Lc, nLc, bc, open, otabu, closed, ctabu, qc, qm, o1, tab, total;
+};
+
+// tab_B > 0: the instance's B x Mp cost table is staged in LDS as well (row
+// pitch Mp), so that the loop touches no global memory but its trace.
+__host__ __device__ inline SoloLayout solo_layout(int32_t Mp, int32_t K, int32_t ncl,
+                                                  int32_t tab_B = 0)
+{
+    SoloLayout L{};
+    uint32_t o = 0;
+    auto take = [&o](uint32_t bytes) {
+        const uint32_t r = o;
+        o += (bytes + 15u) & ~15u;
+        return r;
+    };
+    const uint32_t bins = (uint32_t)(kSoloWaves * kSoloJ * K);
+    L.Ld = take(8u * (uint32_t)(K + 1));
+    L.nLd = take(8u * (uint32_t)(K + 1));
+    L.bd = take(8u * bins);
+    L.b1 = take(4u * (uint32_t)Mp);
+    L.b2 = take(4u * (uint32_t)Mp);
+    L.Lc = take(4u * (uint32_t)(K + 1));
+    L.nLc = take(4u * (uint32_t)(K + 1));
+    L.bc = take(4u * bins);
+    L.open = take(4u * (uint32_t)K);
+    L.otabu = take(4u * (uint32_t)K);
+    L.closed = take(4u * (uint32_t)ncl);
+    L.ctabu = take(4u * (uint32_t)ncl);
+    L.qc = take(4u * kSoloWaves * kSoloQ);
+    L.qm = take(4u * kSoloWaves * kSoloQ);
+    L.o1 = take((uint32_t)Mp);
+    L.tab = take(4u * (uint32_t)tab_B * (uint32_t)Mp);
+    L.total = o;
+    return L;
+}
+
+template <bool TAB>
+__global__ __launch_bounds__(kSoloBlock) void k_solo(const InstDesc *__restrict__ descs,
+                                                     const Tile *__restrict__ order)
+{
+    const InstDesc &d = descs[order[blockIdx.x].inst];
+    if (!d.active || d.N < 1) return;
+    const int32_t K = d.K, M = d.M, Mp = d.Mp, R = d.R, N = d.N, T = d.T, mode = d.mode;
+    const int32_t nclosed = d.nclosed, ncl = max(nclosed, 1);
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SoloLayout LO = solo_layout(Mp, K, ncl, TAB ? d.B : 0);
+    // the cost table: device memory, or its LDS copy (row pitch Mp)
+    int32_t *s_tab = reinterpret_cast<int32_t *>(smem + LO.tab);
+    const int32_t *Ctab = TAB ? s_tab : d.C;
+    const int64_t ldc = TAB ? (int64_t)Mp : d.ldc;
+    u64 *s_Ld = reinterpret_cast<u64 *>(smem + LO.Ld);
+    u64 *s_nLd = reinterpret_cast<u64 *>(smem + LO.nLd);
+    int32_t *s_b1 = reinterpret_cast<int32_t *>(smem + LO.b1);
+    int32_t *s_b2 = reinterpret_cast<int32_t *>(smem + LO.b2);
+    int32_t *s_Lc = reinterpret_cast<int32_t *>(smem + LO.Lc);
+    int32_t *s_nLc = reinterpret_cast<int32_t *>(smem + LO.nLc);
+    int32_t *s_open = reinterpret_cast<int32_t *>(smem + LO.open);
+    int32_t *s_otabu = reinterpret_cast<int32_t *>(smem + LO.otabu);
+    int32_t *s_closed = reinterpret_cast<int32_t *>(smem + LO.closed);
+    int32_t *s_ctabu = reinterpret_cast<int32_t *>(smem + LO.ctabu);
+    unsigned char *s_o1 = smem + LO.o1;
+    // this wave's bins and hit queue
+    int32_t *bc = reinterpret_cast<int32_t *>(smem + LO.bc) + wave * kSoloJ * K;
+    u64 *bd = reinterpret_cast<u64 *>(smem + LO.bd) + wave * kSoloJ * K;
+    int32_t *qc = reinterpret_cast<int32_t *>(smem + LO.qc) + wave * kSoloQ;
+    int32_t *qm = reinterpret_cast<int32_t *>(smem + LO.qm) + wave * kSoloQ;
+    __shared__ Candidate s_red[kSoloWaves];
+    __shared__ SolveState s_st;
+    __shared__ int32_t s_valid, s_improved;
+
+    // the state of S_1 (engine_init), the lists and their expiries
+    for (int32_t m = threadIdx.x; m < Mp; m += kSoloBlock) {
+        s_b1[m] = d.b1[m];
+        s_b2[m] = d.b2[m];
+        s_o1[m] = (unsigned char)(d.o1[m] & 0xFF);
+    }
+    for (int32_t k = threadIdx.x; k < K; k += kSoloBlock) {
+        s_open[k] = d.open[k];
+        s_otabu[k] = d.open_tabu[k];
+    }
+    for (int32_t js = threadIdx.x; js < ncl; js += kSoloBlock) {
+        s_closed[js] = d.closed[js];
+        s_ctabu[js] = d.closed_tabu[js];
+    }
+    for (int32_t k = threadIdx.x; k <= K; k += kSoloBlock) {
+        int32_t c;
+        int64_t dd;
+        acc_sum(d.acc[1], K, k, c, dd);
+        s_Lc[k] = c;
+        s_Ld[k] = (u64)dd;
+    }
+    if (TAB) {
+        // (padding columns M .. Mp-1 are never compared: their b2 is INT32_MIN)
+        const int32_t B = d.B, nq4 = Mp >> 2;
+        for (int32_t e = threadIdx.x; e < B * nq4; e += kSoloBlock) {
+            const int32_t b = e / nq4, q = e - b * nq4;
+            v4i v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t m = 4 * q + i;
+                v[i] = m < M ? d.C[(int64_t)b * d.ldc + m] : INT32_MAX;
+            }
+            *reinterpret_cast<v4i *>(s_tab + (int64_t)b * Mp + 4 * q) = v;
+        }
+    }
+    if (threadIdx.x == 0) s_st = *d.st;
+    __syncthreads();
+
+    const int32_t nq = Mp >> 2;
+    const int32_t ngroups = nclosed > 0 ? (nclosed + kSoloJ - 1) / kSoloJ : 0;
+    for (int32_t t = 1; t <= N; ++t) {
+        if (s_st.stopped) {
+            // local search ended earlier: the iteration makes no move
+            if (threadIdx.x == 0) write_record(d, t, s_st, 0, -1, -1);
+            continue;
+        }
+        const int32_t Gc = s_Lc[0];
+        const int64_t Gd = (int64_t)s_Ld[0];
+        const int32_t cur_c = s_st.cur_cov, best_c = s_st.best_cov;
+        const int64_t cur_d = s_st.cur_dist, best_d = s_st.best_dist;
+        Candidate mine = no_cand();
+
+        // ---- sweep: kSoloJ closed rows per wave at a time
+        for (int32_t g = wave; g < ngroups; g += kSoloWaves) {
+            int32_t js[kSoloJ], jr[kSoloJ];
+            bool rv[kSoloJ];
+            const v4i *rows[kSoloJ];
+#pragma unroll
+            for (int r = 0; r < kSoloJ; ++r) {
+                js[r] = g * kSoloJ + r;
+                rv[r] = js[r] < nclosed;
+                jr[r] = s_closed[rv[r] ? js[r] : 0];
+                rows[r] = reinterpret_cast<const v4i *>(Ctab + (int64_t)jr[r] * ldc);
+            }
+            for (int32_t idx = lane; idx < kSoloJ * K; idx += 64) {
+                bc[idx] = 0;
+                bd[idx] = 0;
+            }
+            int32_t t1c[kSoloJ];
+            int64_t t1d[kSoloJ];
+#pragma unroll
+            for (int r = 0; r < kSoloJ; ++r) {
+                t1c[r] = 0;
+                t1d[r] = 0;
+            }
+            int32_t qlen = 0;
+            // score queue entries [0, n), one per lane (a macro: the per-row
+            // sums stay in registers)
+#define FS_SOLO_DRAIN(n)                                                                   \
+    do {                                                                                   \
+        __builtin_amdgcn_wave_barrier();                                                   \
+        if (lane < (n)) {                                                                  \
+            const int32_t c_ = qc[lane], mr_ = qm[lane];                                   \
+            const int32_t m_ = mr_ & 0xFFFFFF, r_ = mr_ >> 24;                             \
+            const int32_t b1_ = s_b1[m_], b2_ = s_b2[m_], o1_ = s_o1[m_];                  \
+            const int32_t g1c_ = b1_ <= R, g1d_ = g1c_ ? b1_ : 0;                          \
+            const int32_t g2c_ = b2_ <= R, g2d_ = g2c_ ? b2_ : 0;                          \
+            const int32_t v1_ = min(c_, b1_), u_ = max(c_, b1_);                           \
+            const int32_t cv_ = v1_ <= R;                                                  \
+            const int32_t tc_ = cv_ - g1c_, td_ = (cv_ ? v1_ : 0) - g1d_;                  \
+            _Pragma("unroll") for (int q_ = 0; q_ < kSoloJ; ++q_)                          \
+            {                                                                              \
+                t1c[q_] += r_ == q_ ? tc_ : 0;                                             \
+                t1d[q_] += r_ == q_ ? (int64_t)td_ : 0;                                    \
+            }                                                                              \
+            const int32_t cu_ = u_ <= R;                                                   \
+            const int32_t dc_ = cu_ - g2c_, dd_ = (cu_ ? u_ : 0) - g2d_;                   \
+            if (dc_ | dd_) {                                                               \
+                atomicAdd(bc + r_ * K + o1_, dc_);                                         \
+                atomicAdd(bd + r_ * K + o1_, (u64)(int64_t)dd_);                           \
+            }                                                                              \
+        }                                                                                  \
+        __builtin_amdgcn_wave_barrier();                                                   \
+    } while (0)
+            for (int32_t q0 = 0; q0 < nq; q0 += 64 * kSoloU) {
+                v4i cv[kSoloU][kSoloJ], vb2[kSoloU];
+#pragma unroll
+                for (int u = 0; u < kSoloU; ++u) {
+                    const int32_t q = min(q0 + u * 64 + lane, nq - 1);
+#pragma unroll
+                    for (int r = 0; r < kSoloJ; ++r)
+                        cv[u][r] = TAB ? rows[r][q]
+                                       : *(const __attribute__((address_space(1))) v4i *)(rows[r] + q);
+                    vb2[u] = *reinterpret_cast<const v4i *>(s_b2 + 4 * q);
+                }
+#pragma unroll
+                for (int u = 0; u < kSoloU; ++u) {
+                    const int32_t q = q0 + u * 64 + lane;
+                    if (q >= nq) vb2[u] = (v4i)(INT32_MIN);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                        for (int r = 0; r < kSoloJ; ++r) {
+                            const bool hit = rv[r] && cv[u][r][e] < vb2[u][e];
+                            const u64 mask = __builtin_amdgcn_ballot_w64(hit);
+                            if (mask == 0) continue;
+                            if (hit) {
+                                const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(mask >> 32),
+                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)qlen));
+                                qc[at] = cv[u][r][e];
+                                qm[at] = (4 * q + e) | (r << 24);
+                            }
+                            qlen = __builtin_amdgcn_readfirstlane(
+                                qlen + (int32_t)__builtin_popcountll(mask));
+                            if (qlen >= 64) {
+                                FS_SOLO_DRAIN(64);
+                                qlen -= 64;
+                                int32_t c2 = 0, m2 = 0;
+                                if (lane < qlen) {
+                                    c2 = qc[64 + lane];
+                                    m2 = qm[64 + lane];
+                                }
+                                __builtin_amdgcn_wave_barrier();
+                                if (lane < qlen) {
+                                    qc[lane] = c2;
+                                    qm[lane] = m2;
+                                }
+                                __builtin_amdgcn_wave_barrier();
+                            }
+                        }
+                    }
+                }
+            }
+            if (qlen > 0) FS_SOLO_DRAIN(qlen);
+#undef FS_SOLO_DRAIN
+            __builtin_amdgcn_wave_barrier();
+            // the rows' common terms, then this group's moves
+#pragma unroll
+            for (int r = 0; r < kSoloJ; ++r) {
+                t1c[r] = wave_sum_i32(t1c[r]);
+                t1d[r] = wave_sum_i64(t1d[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < kSoloJ; ++r) {
+                if (!rv[r]) continue;
+                for (int32_t k = lane; k < K; k += 64) {
+                    const int32_t idx = r * K + k;
+                    const int32_t cov = Gc + s_Lc[1 + k] + t1c[r] + bc[idx];
+                    const int64_t dist = Gd + (int64_t)s_Ld[1 + k] + t1d[r] + (int64_t)bd[idx];
+                    const bool adm = mode == 1 ? better(cov, dist, cur_c, cur_d)
+                                               : (s_otabu[k] < t && s_ctabu[js[r]] < t) ||
+                                                     better(cov, dist, best_c, best_d);
+                    if (adm) {
+                        Candidate c;
+                        c.cov = cov;
+                        c.dist = dist;
+                        c.i_base = s_open[k];
+                        c.j_base = jr[r];
+                        c.slots = (uint32_t)k | ((uint32_t)js[r] << kSlotBits);
+                        c.key = 0;
+                        if (cand_better<false>(c, mine)) mine = c;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        mine = wave_best<false>(mine);
+        if (lane == 0) s_red[wave] = mine;
+        __syncthreads();
+
+        // ---- argmax and commit (the multi-workgroup refresh's leader)
+        if (threadIdx.x == 0) {
+            Candidate best = s_red[0];
+            for (int w = 1; w < kSoloWaves; ++w)
+                if (cand_better<false>(s_red[w], best)) best = s_red[w];
+            SolveState s = s_st;
+            const bool valid = cand_valid(best);
+            int32_t improved = 0;
+            if (!valid && mode == 1) {
+                s.stopped = 1;   // local optimum: the placement stays as it is
+                write_record(d, t, s, 0, -1, -1);
+            } else {
+                if (valid) {
+                    s.cur_cov = best.cov;
+                    s.cur_dist = best.dist;
+                    if (better(best.cov, best.dist, s.best_cov, s.best_dist)) {
+                        s.best_cov = best.cov;
+                        s.best_dist = best.dist;
+                        s.best_iter = t;
+                        improved = 1;
+                    }
+                    s.have_last = 1;
+                    s.last_key = best.key;
+                    const int32_t i_slot = cand_i_slot(best), j_slot = cand_j_slot(best);
+                    s_open[i_slot] = best.j_base;
+                    s_otabu[i_slot] = t + T;
+                    s_closed[j_slot] = best.i_base;
+                    s_ctabu[j_slot] = t + T;
+                }
+                write_record(d, t, s, valid, best.i_base, best.j_base);
+            }
+            s_st = s;
+            s_valid = valid;
+            s_improved = improved;
+        }
+        for (int32_t k = threadIdx.x; k <= K; k += kSoloBlock) {
+            s_nLc[k] = 0;
+            s_nLd[k] = 0;
+        }
+        __syncthreads();
+        if (!s_valid) continue;   // no move: the placement and its state are unchanged
+        if (s_improved)
+            for (int32_t k = threadIdx.x; k < K; k += kSoloBlock) d.best_open[k] = s_open[k];
+
+        // ---- state of the new placement
+        int32_t gc = 0;
+        int64_t gd = 0;
+        for (int32_t m = threadIdx.x; m < M; m += kSoloBlock) {
+            const int32_t *col = Ctab + m;
+            int32_t v1 = INT32_MAX, i1 = INT32_MAX, s1 = 0, v2 = INT32_MAX;
+            constexpr int UNR = 16;
+            for (int32_t k0 = 0; k0 < K; k0 += UNR) {
+                int32_t c[UNR], id[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int32_t k = k0 + u;
+                    id[u] = k < K ? s_open[k] : 0;
+                    c[u] = k < K ? col[(int64_t)id[u] * ldc] : INT32_MAX;
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int32_t k = k0 + u;
+                    if (k < K) {
+                        if (c[u] < v1 || (c[u] == v1 && id[u] < i1)) {
+                            v2 = v1;
+                            v1 = c[u];
+                            i1 = id[u];
+                            s1 = k;
+                        } else if (c[u] < v2) {
+                            v2 = c[u];
+                        }
+                    }
+                }
+            }
+            s_b1[m] = v1;
+            s_b2[m] = v2;
+            s_o1[m] = (unsigned char)s1;
+            const int32_t g1c = v1 <= R, g1d = g1c ? v1 : 0;
+            const int32_t g2c = v2 <= R, g2d = g2c ? v2 : 0;
+            const int32_t dc = g2c - g1c, dd = g2d - g1d;
+            if (dc | dd) {
+                atomicAdd(&s_nLc[1 + s1], dc);
+                atomicAdd(&s_nLd[1 + s1], (u64)(int64_t)dd);
+            }
+            gc += g1c;
+            gd += g1d;
+        }
+        gc = wave_sum_i32(gc);
+        gd = wave_sum_i64(gd);
+        if (lane == 0) {
+            atomicAdd(&s_nLc[0], gc);
+            atomicAdd(&s_nLd[0], (u64)gd);
+        }
+        __syncthreads();
+        // the recounted value must be the chosen move's score
+        if (threadIdx.x == 0 && (s_nLc[0] != s_st.cur_cov || (int64_t)s_nLd[0] != s_st.cur_dist) &&
+            !s_st.error) {
+            s_st.error = 1;
+            s_st.err_iter = t + 1;
+        }
+        for (int32_t k = threadIdx.x; k <= K; k += kSoloBlock) {
+            s_Lc[k] = s_nLc[k];
+            s_Ld[k] = s_nLd[k];
+        }
+        __syncthreads();
+    }
+
+    // back to device memory: what the outputs read (search state, best
+    // placement) and the final placement's lists and value
+    for (int32_t k = threadIdx.x; k < K; k += kSoloBlock) {
+        d.open[k] = s_open[k];
+        d.open_tabu[k] = s_otabu[k];
+    }
+    for (int32_t js = threadIdx.x; js < ncl; js += kSoloBlock) {
+        d.closed[js] = s_closed[js];
+        d.closed_tabu[js] = s_ctabu[js];
+    }
+    Acc *fin = d.acc[(N + 1) & 1];
+    for (int32_t q = threadIdx.x; q < kStripes * (K + 1); q += kSoloBlock) {
+        const bool s0 = q < K + 1;
+        fin[q].cov = s0 ? (u64)(int64_t)s_Lc[q] : 0;
+        fin[q].dist = s0 ? s_Ld[q] : 0;
+    }
+    if (threadIdx.x == 0) *d.st = s_st;
+}
+
 // ---------------------------------------------------------------- dispatch
 
 // A launch that carries the timing events when there are any (the dispatch
@@ -2575,6 +2989,22 @@ fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t s
     launch_timed(refresh_kernel(c), dim3(t.nrefresh), dim3(c.refresh_wide ? kWideBlock : kBlock),
                  (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), t.desc,
                  t.single ? nullptr : t.refresh, step);
+    FS_HIP(hipGetLastError());
+    timed.used();
+    return FS_OK;
+}
+
+size_t solo_lds_of(int32_t Mp, int32_t K, int32_t nclosed, int32_t tab_B)
+{
+    return solo_layout(Mp, K, std::max(nclosed, 1), tab_B).total;
+}
+
+fs_status engine_persistent(const EngineTables &t, const EngineConfig &c, hipStream_t s)
+{
+    if (t.nsolo == 0) return FS_OK;
+    TimedLaunch timed(0);
+    launch_timed(c.solo_tab ? k_solo<true> : k_solo<false>, dim3(t.nsolo), dim3(kSoloBlock),
+                 c.solo_lds, s, timed.start(), timed.stop(), t.desc, t.solo);
     FS_HIP(hipGetLastError());
     timed.used();
     return FS_OK;

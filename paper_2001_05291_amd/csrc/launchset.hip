@@ -100,6 +100,41 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     // (forms without a 1024-thread kernel launch 256 threads)
     cfg.wide = env_int("FS_SWEEP_WIDE", cfg.J <= 2 && sweep.size() < 1024 &&
                                             chunks[n / 2] >= 8192) != 0;
+    // the persistent search (one workgroup per instance for the whole loop):
+    // homogeneous instances of modes 0 and 1 with 16-byte rows whose state fits
+    // LDS with two workgroups per CU; the default for a large batch or small
+    // instances (where one launch per iteration is mostly launch overhead)
+    // (measured: a whole 200-iteration search of a 400 x 5,000 instance in one
+    // workgroup is slower than the ragged batch's per-iteration launches, so
+    // the persistent search is the default for small instances only, whose
+    // tables it stages in LDS when they fit)
+    {
+        bool can = !cfg.typed && !cfg.sparse && vec4;
+        size_t lds = 0, lds_tab = 0;
+        int64_t work_max = 0;
+        for (int i = 0; i < n && can; ++i) {
+            const InstSpec &p = specs[i];
+            can = p.mode <= 1 && p.K <= kSoloMaxKPersist && !p.sc_cov && p.M < kSoloMaxMissions;
+            lds = std::max(lds, solo_lds_of(Mp[i], p.K, p.B - p.K));
+            lds_tab = std::max(lds_tab, solo_lds_of(Mp[i], p.K, p.B - p.K, p.B));
+            work_max = std::max(work_max, (int64_t)(p.B - p.K) * Mp[i]);
+        }
+        can = can && lds + 1024 <= (size_t)80 * 1024;
+        const bool pays = work_max <= ((int64_t)1 << 16);
+        cfg.persistent = can && env_int("FS_PERSIST", pays ? 1 : 0) != 0;
+        cfg.solo_tab = cfg.persistent && lds_tab + 1024 <= (size_t)160 * 1024 &&
+                       env_int("FS_PERSIST_TAB", 1) != 0;
+        cfg.solo_lds = (uint32_t)(cfg.solo_tab ? lds_tab : lds);
+    }
+    std::vector<Tile> solo;
+    if (cfg.persistent) {
+        // largest instances first, so that they do not finish last
+        std::vector<int> ord(n);
+        for (int i = 0; i < n; ++i) ord[i] = i;
+        auto work = [&](int i) { return ((int64_t)specs[i].B) * Mp[i]; };
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+        for (int i : ord) solo.push_back(Tile{i, 0, 0, 0});
+    }
     size_t list_ints = 0;
     for (int i = 0; i < n; ++i) {
         if (specs[i].init_host) {
@@ -116,7 +151,8 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     const size_t o_score = o_sweep + a256(sizeof(Tile) * sweep.size());
     const size_t o_refresh = o_score + a256(sizeof(Tile) * std::max<size_t>(score.size(), 1));
     const size_t o_rank = o_refresh + a256(sizeof(Tile) * refresh.size());
-    const size_t o_scores = o_rank + a256(sizeof(Tile) * std::max<size_t>(rank_rows.size(), 1));
+    const size_t o_solo = o_rank + a256(sizeof(Tile) * std::max<size_t>(rank_rows.size(), 1));
+    const size_t o_scores = o_solo + a256(sizeof(Tile) * std::max<size_t>(solo.size(), 1));
     const size_t o_errors = o_scores + a256(sizeof(fs_score) * n);
     const size_t o_lists = o_errors + a256(sizeof(int32_t) * n);
     const size_t o_ws = o_lists + a256(4 * std::max<size_t>(list_ints, 1));
@@ -199,6 +235,7 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     memcpy(head.data() + o_refresh, refresh.data(), sizeof(Tile) * refresh.size());
     if (!rank_rows.empty())
         memcpy(head.data() + o_rank, rank_rows.data(), sizeof(Tile) * rank_rows.size());
+    if (!solo.empty()) memcpy(head.data() + o_solo, solo.data(), sizeof(Tile) * solo.size());
     FS_HIP(hipMemcpyAsync(base, head.data(), head.size(), hipMemcpyHostToDevice, s));
     // the host image is pageable and local: finish the copy before it goes
     FS_HIP(hipStreamSynchronize(s));
@@ -213,6 +250,8 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     t.refresh = (const Tile *)(base + o_refresh);
     t.nrefresh = (int)refresh.size();
     t.single = n == 1;
+    t.solo = (const Tile *)(base + o_solo);
+    t.nsolo = (int)solo.size();
     ls.rank_rows = (const Tile *)(base + o_rank);
     ls.nrank_rows = (int)rank_rows.size();
     ls.d_scores = (fs_score *)(base + o_scores);
@@ -348,6 +387,7 @@ fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s)
     if (ls.any_typed) FS_TRY(engine_fleet_lists(ls.tabs, s));
     FS_TRY(engine_init(ls.tabs, ls.cfg, 0, s));
     if (ls.cfg.sparse && N >= 1) FS_TRY(engine_sparse_prepare(ls.tabs, s));
+    if (ls.cfg.persistent) return N >= 1 ? engine_persistent(ls.tabs, ls.cfg, s) : FS_OK;
     if (N >= 1) FS_TRY(tune_sweep(ls, s));
     for (int32_t t = 1; t <= N; ++t) {
         FS_TRY(engine_sweep(ls.tabs, ls.cfg, t, s));

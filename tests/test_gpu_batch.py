@@ -27,9 +27,11 @@ def same(a, b):
     assert np.array_equal(a.assign.cpu().numpy(), b.assign.cpu().numpy())
 
 
-@pytest.mark.parametrize("refresh_wide", ["0", "1"])
-def test_batch_random_ragged_matches_solo_and_oracle(fs, monkeypatch, refresh_wide):
+@pytest.mark.parametrize("refresh_wide,persist", [("0", "0"), ("1", "0"), ("0", "1")])
+def test_batch_random_ragged_matches_solo_and_oracle(fs, monkeypatch, refresh_wide, persist):
+    # per-iteration launches (both refresh widths) and the persistent search
     monkeypatch.setenv("FS_REFRESH_WIDE", refresh_wide)
+    monkeypatch.setenv("FS_PERSIST", persist)
     rng = np.random.default_rng(71)
     items, hosts = [], []
     for i in range(40):

@@ -241,6 +241,32 @@ def test_refresh_forms_medium(split4):
     assert_same_result(g, o, C, c["R"])
 
 
+@pytest.mark.parametrize("persist,tab", [(0, 1), (1, 1), (1, 0)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_persistent_search_small_and_random(persist, tab, mode):
+    # the whole search in one workgroup per instance (persistent launch; the
+    # table in LDS or in device memory) against the oracle, and the
+    # per-iteration launches, on the small workload and random tables with
+    # ties and ragged mission counts
+    c = synth.WORKLOADS["small"]
+    _, C = instance_and_table("small")
+    with env(FS_PERSIST=persist, FS_PERSIST_TAB=tab):
+        g, o = run_both(C, c["K"], c["R"], c["T"], c["N"], mode=mode, ldc=(c["M"] + 3) // 4 * 4)
+    assert_same_result(g, o, C, c["R"])
+    rng = np.random.default_rng(900 + 10 * persist + 100 * tab + mode)
+    for trial in range(12):
+        B = int(rng.integers(2, 90))
+        K = int(rng.integers(1, min(B, 64) + 1))
+        M = int(rng.integers(1, 3000))
+        C = rng.integers(0, 400, size=(B, M)).astype(np.int32)
+        R = int(rng.integers(0, 420))
+        init = None if trial % 3 == 0 else np.sort(rng.choice(B, K, replace=False)).astype(np.int32)
+        with env(FS_PERSIST=persist, FS_PERSIST_TAB=tab):
+            g, o = run_both(C, K, R, int(rng.integers(0, 9)), int(rng.integers(1, 60)),
+                            mode=mode, init=init, ldc=(M + 3) // 4 * 4)
+        assert_same_result(g, o, C, R)
+
+
 @pytest.mark.parametrize("cfg", ["small", "medium"])
 def test_local_search_configs(cfg):
     c = synth.WORKLOADS[cfg]

@@ -1,7 +1,7 @@
 """Seeded random searches under random launch geometries: every combination
 of rows per workgroup, loads in flight, queued or in-place scoring,
 1024-thread workgroups, mission splits, refresh width and slot split, dense or
-sparse sweep
+sparse sweep, the persistent search
 and the autotuner gives the oracle's trajectory bit for bit (modes 0-3,
 Section 4.3; random tables, ties, costs beyond 2^26), for single instances,
 ragged batches and typed fleets."""
@@ -21,7 +21,8 @@ from gpu_util import assert_trace_equal, padded_table  # noqa: E402
 fs = None
 
 KEYS = ("FS_SWEEP_J", "FS_SWEEP_U", "FS_SWEEP_QUEUE", "FS_SWEEP_WIDE", "FS_SWEEP_SPLIT",
-        "FS_REFRESH_WIDE", "FS_REFRESH_SPLIT4", "FS_SPARSE", "FS_SPARSE_SPLIT", "FS_AUTOTUNE")
+        "FS_REFRESH_WIDE", "FS_REFRESH_SPLIT4", "FS_SPARSE", "FS_SPARSE_SPLIT", "FS_AUTOTUNE",
+        "FS_PERSIST", "FS_PERSIST_TAB")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -58,6 +59,10 @@ def draw_env(rng):
         env["FS_REFRESH_SPLIT4"] = int(rng.integers(0, 2))
     if rng.random() < 0.4:
         env["FS_SPARSE"] = int(rng.integers(0, 2))
+    if rng.random() < 0.5:
+        env["FS_PERSIST"] = int(rng.integers(0, 2))
+    if rng.random() < 0.3:
+        env["FS_PERSIST_TAB"] = int(rng.integers(0, 2))
     if rng.random() < 0.3:
         env["FS_SPARSE_SPLIT"] = int(rng.integers(1, 4))
     env["FS_AUTOTUNE"] = int(rng.integers(0, 2))
