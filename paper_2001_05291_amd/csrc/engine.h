@@ -36,6 +36,11 @@ struct InstDesc {
     unsigned char *lst_id;
     int32_t *mm_cost;
     unsigned char *mm_id;
+    // packed lists (every cost below 2^26 - 1: any haversine table): each
+    // entry is one 32-bit key (cost << 6 | local id) in lst_cost / mm_cost,
+    // and lst_id / mm_id are unused; *wide is set by a build that met a wider
+    // cost (the lists are then built again unpacked)
+    int32_t *wide;
     int32_t *base_slot;      // B: closed slot (>= 0) or -1 - open slot
     int32_t nclosed, chunk, nsplit, ngroups;
     int32_t active;          // 0: every kernel skips this instance
@@ -119,6 +124,7 @@ struct EngineConfig {
     bool refresh_wide = false;
     int Kmax = 1;
     bool sparse = false;   // the sparse sweep (single homogeneous instance)
+    bool sparse_packed = false;   // its lists hold packed 32-bit keys
     // persistent search: one workgroup per instance runs all N iterations
     // (k_solo); solo_lds is its dynamic LDS, sized for the largest instance
     bool persistent = false;
@@ -185,7 +191,9 @@ fs_status engine_fleet_lists(const EngineTables &t, hipStream_t s);
 // launch step at which the instances' iteration 0 ends (their start_step).
 fs_status engine_init(const EngineTables &t, const EngineConfig &c, int32_t step0, hipStream_t s);
 // Sparse sweep: the sorted lists and the base -> slot map (after engine_init).
-fs_status engine_sparse_prepare(const EngineTables &t, hipStream_t s);
+// The lists are packed when every cost allows (c.sparse_packed tells the
+// sweep which form was built).
+fs_status engine_sparse_prepare(const EngineTables &t, EngineConfig &c, hipStream_t s);
 // Scores every swap of every instance and keeps each row group's best
 // admissible move.
 fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t step,

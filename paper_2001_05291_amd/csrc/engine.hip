@@ -1581,11 +1581,15 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
 // dense sweep's (the same integer arithmetic on the same elements), so the
 // scores are identical.
 
+// Costs below kNarrowTop (2^26 - 1) fit a 32-bit (cost << 6 | id) key.
+constexpr uint32_t kNarrowTop = (1u << 26) - 1;
+
 // Sorted lists of one block x 64 missions: the C tile is staged in LDS, each
 // wave sorts a mission's 64 (cost, local id) keys across its lanes (bitonic,
 // ascending; the sign bit is flipped so that the unsigned key order is the
 // signed cost order), and the sorted columns go out rank-major.  Bases past B
 // and missions past M sort last with cost INT32_MAX, which no b2 exceeds.
+template <bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restrict__ descs)
 {
     const InstDesc &d = descs[0];
@@ -1623,7 +1627,6 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     // [0, 2^26 - 1) or is the sentinel, (cost << 6 | id) fits 32 bits with
     // the sentinel as 2^26 - 1, in the same order; a haversine round trip is
     // below 6.1e7 m < 2^26 - 1, so real tables take this path)
-    constexpr uint32_t kNarrowTop = (1u << 26) - 1;
     constexpr int PER_WAVE = 64 / (kBlock / 64), IL = 4;
     for (int i0 = 0; i0 < PER_WAVE; i0 += IL) {
         int32_t cst[IL];
@@ -1684,28 +1687,45 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
         }
     }
     __syncthreads();
+    // Packed keys: (cost << 6 | id), the sentinel as kNarrowTop << 6 | id (no
+    // b2 threshold reaches it); a cost that does not fit sets the wide flag
+    // (the lists are then built again unpacked).
+    if (PACKED) {
+        bool bad = false;
+        for (int32_t u = threadIdx.x; u < kSparseW * 64; u += kBlock) {
+            const int32_t c = s_cost[u >> 6][u & 63];
+            bad = bad || (c != INT32_MAX && (uint32_t)c >= kNarrowTop);
+        }
+        if (__builtin_amdgcn_ballot_w64(bad) != 0 && (threadIdx.x & 63) == 0)
+            atomicOr(d.wide, 1);
+    }
+    auto key_of = [&](int32_t r, int32_t mm) {
+        const int32_t c = s_cost[r][mm];
+        return (int32_t)(((c == INT32_MAX ? kNarrowTop : (uint32_t)c) << 6) |
+                         (uint32_t)s_id[r][mm]);
+    };
     // The head ranks rank-major: four consecutive missions of one rank per
-    // thread, one 16-byte store of costs and one 4-byte store of ids (Mp is a
-    // multiple of 4, so a quad lies wholly inside or outside the padded
-    // mission range, and every quad's address is 16- and 4-byte aligned).
+    // thread, one 16-byte store of costs (or keys) and one 4-byte store of ids
+    // (Mp is a multiple of 4, so a quad lies wholly inside or outside the
+    // padded mission range, and every quad's address is 16- and 4-byte
+    // aligned).
     const int64_t Mp = d.Mp;
     for (int32_t u = threadIdx.x; u < kSparseHead * 16; u += kBlock) {
         const int32_t r = u >> 4, mm = (u & 15) * 4, m = mg * 64 + mm;
         if (m < Mp) {
             const int64_t at = ((int64_t)q * kSparseHead + r) * Mp + m;
             v4i c;
-            c[0] = s_cost[r][mm];
-            c[1] = s_cost[r][mm + 1];
-            c[2] = s_cost[r][mm + 2];
-            c[3] = s_cost[r][mm + 3];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) c[e] = PACKED ? key_of(r, mm + e) : s_cost[r][mm + e];
             *reinterpret_cast<v4i *>(d.lst_cost + at) = c;
-            *reinterpret_cast<uint32_t *>(d.lst_id + at) =
-                *reinterpret_cast<const uint32_t *>(&s_id[r][mm]);
+            if (!PACKED)
+                *reinterpret_cast<uint32_t *>(d.lst_id + at) =
+                    *reinterpret_cast<const uint32_t *>(&s_id[r][mm]);
         }
     }
     // Every rank mission-major: sixteen consecutive ranks of one mission per
-    // thread, four 16-byte stores of costs and one of ids (a wave writes 4 KB
-    // of consecutive costs).
+    // thread, four 16-byte stores of costs (or keys) and one of ids (a wave
+    // writes 4 KB of consecutive entries).
     for (int32_t u = threadIdx.x; u < 64 * (kSparseW / 16); u += kBlock) {
         const int32_t mm = u / (kSparseW / 16), r0 = (u % (kSparseW / 16)) * 16;
         const int32_t m = mg * 64 + mm;
@@ -1715,18 +1735,22 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
             for (int v = 0; v < 4; ++v) {
                 v4i c;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) c[e] = s_cost[r0 + 4 * v + e][mm];
+                for (int e = 0; e < 4; ++e)
+                    c[e] = PACKED ? key_of(r0 + 4 * v + e, mm) : s_cost[r0 + 4 * v + e][mm];
                 *reinterpret_cast<v4i *>(d.mm_cost + at + 4 * v) = c;
             }
-            v4i ids;
+            if (!PACKED) {
+                v4i ids;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                uint32_t w = 0;
+                for (int v = 0; v < 4; ++v) {
+                    uint32_t w = 0;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) w |= (uint32_t)s_id[r0 + 4 * v + e][mm] << (8 * e);
-                ids[v] = (int32_t)w;
+                    for (int e = 0; e < 4; ++e)
+                        w |= (uint32_t)s_id[r0 + 4 * v + e][mm] << (8 * e);
+                    ids[v] = (int32_t)w;
+                }
+                *reinterpret_cast<v4i *>(d.mm_id + at) = ids;
             }
-            *reinterpret_cast<v4i *>(d.mm_id + at) = ids;
         }
     }
 }
@@ -1817,7 +1841,26 @@ constexpr int kSparseQ = 128;   // queued walks per wave: below 64 + 64 before a
 // the rare case that it needs more.  A wave thus waits for one round of
 // loads per 256 missions plus one per 64 continued walks, instead of one
 // per rank batch of every group of 64 missions.
-template <int BS>
+// Packed lists: a key is below the threshold of b2 exactly when its cost is
+// below b2 (sentinel keys, kNarrowTop << 6 | id, never are).
+__device__ __forceinline__ uint32_t packed_threshold(int32_t b2)
+{
+    return b2 <= 0 ? 0u : ((uint32_t)b2 >= kNarrowTop ? kNarrowTop << 6 : (uint32_t)b2 << 6);
+}
+
+#define FS_SPARSE_KEY(key)                                                                 \
+    do {                                                                                   \
+        if (act && (key) < thr) {                                                          \
+            const int32_t row = s_rowof[(key) & 63];                                       \
+            if (row >= 0)                                                                  \
+                visit_sparse((int32_t)((key) >> 6), b1, b2, o1, g1c, g1d, g2c, g2d, R,     \
+                             s_t1c + row, s_t1d + row, L.bc + row * K, L.bd + row * K);    \
+        } else {                                                                           \
+            act = false;                                                                   \
+        }                                                                                  \
+    } while (0)
+
+template <int BS, bool PACKED>
 __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restrict__ descs,
                                                      const Tile *__restrict__ tiles, int32_t step)
 {
@@ -1879,9 +1922,10 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
         const int32_t b1 = ((const gi32 *)d.b1)[m], b2 = ((const gi32 *)d.b2)[m],
                       o1 = ((const gi32 *)d.o1)[m];
         v4i c0 = myc[0], c1 = myc[1];
-        uint64_t ids = myi[0];
+        uint64_t ids = PACKED ? 0 : myi[0];
         const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
         const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+        const uint32_t thr = packed_threshold(b2);
         bool act = have;
         for (int32_t r8 = 0; r8 < kSparseW / 8; ++r8) {
             if (r8 > 0) {
@@ -1889,7 +1933,7 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
                 if (act) {
                     c0 = myc[2 * r8];
                     c1 = myc[2 * r8 + 1];
-                    ids = myi[r8];
+                    if (!PACKED) ids = myi[r8];
                 }
             }
             int32_t cs[8];
@@ -1901,7 +1945,11 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 if (r8 == 0 && e < kSparseHead) continue;
-                FS_SPARSE_STEP(cs[e], (int32_t)((ids >> (8 * e)) & 0xFF));
+                if (PACKED) {
+                    FS_SPARSE_KEY((uint32_t)cs[e]);
+                } else {
+                    FS_SPARSE_STEP(cs[e], (int32_t)((ids >> (8 * e)) & 0xFF));
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -1916,7 +1964,7 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
 #pragma unroll
         for (int r = 0; r < kSparseHead; ++r) {
             hcs[r] = *(const gv4i *)(hc + r * Mp + mc);
-            hid[r] = *(const gu32 *)(hi + r * Mp + mc);
+            hid[r] = PACKED ? 0u : *(const gu32 *)(hi + r * Mp + mc);
         }
         const v4i vb1 = *(const gv4i *)(d.b1 + mc), vb2 = *(const gv4i *)(d.b2 + mc),
                   vo1 = *(const gv4i *)(d.o1 + mc);
@@ -1925,10 +1973,16 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
             const int32_t b1 = vb1[e], b2 = in ? vb2[e] : INT32_MIN, o1 = vo1[e];
             const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
             const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
+            const uint32_t thr = packed_threshold(b2);
             bool act = in;
 #pragma unroll
-            for (int r = 0; r < kSparseHead; ++r)
-                FS_SPARSE_STEP(hcs[r][e], (int32_t)((hid[r] >> (8 * e)) & 0xFF));
+            for (int r = 0; r < kSparseHead; ++r) {
+                if (PACKED) {
+                    FS_SPARSE_KEY((uint32_t)hcs[r][e]);
+                } else {
+                    FS_SPARSE_STEP(hcs[r][e], (int32_t)((hid[r] >> (8 * e)) & 0xFF));
+                }
+            }
             // walks that go on past the head join the queue
             const u64 mask = __builtin_amdgcn_ballot_w64(act);
             if (mask == 0) continue;
@@ -1977,6 +2031,7 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
 }
 
 #undef FS_SPARSE_STEP
+#undef FS_SPARSE_KEY
 
 // Scores one base block from its sums over the mission chunks (added by the
 // sweep's chunks) and clears them for the next iteration (all kSparseW rows:
@@ -2001,15 +2056,29 @@ __global__ __launch_bounds__(BS) void k_score_sparse(const InstDesc *__restrict_
     __shared__ int64_t s_t1d[kSparseW];
     __shared__ int32_t s_nrows;
     __shared__ Candidate s_red[BS / 64 + 1];
+    // the block's sums go out with the row and slot loads and are waited for
+    // once
+    constexpr int PER = (kSparseW * (kSparseMaxK + 1) + BS - 1) / BS;
+    const int64_t base = (int64_t)tl.g * kSparseW * K1;
+    int32_t pcv[PER];
+    int64_t pdv[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int32_t idx = threadIdx.x + i * BS;
+        pcv[i] = idx < kSparseW * K1 ? d.part_cov[base + idx] : 0;
+        pdv[i] = idx < kSparseW * K1 ? d.part_dist[base + idx] : 0;
+    }
     if (threadIdx.x < kSparseW)
         sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
     load_slot_inputs(d, t, L, false);
     __syncthreads();
     const int32_t nrows = s_nrows;
-    const int64_t base = (int64_t)tl.g * kSparseW * K1;
-    for (int32_t idx = threadIdx.x; idx < kSparseW * K1; idx += BS) {
-        const int32_t c = d.part_cov[base + idx];
-        const int64_t dd = d.part_dist[base + idx];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int32_t idx = threadIdx.x + i * BS;
+        if (idx >= kSparseW * K1) continue;
+        const int32_t c = pcv[i];
+        const int64_t dd = pdv[i];
         d.part_cov[base + idx] = 0;
         d.part_dist[base + idx] = 0;
         if (idx >= nrows * K1) continue;
@@ -2752,6 +2821,7 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
         n += align_up(4 * head, 256) + align_up(head, 256);   // sorted heads: costs, ids
         n += align_up(4 * lst, 256) + align_up(lst, 256);     // sorted lists: costs, ids
         n += align_up(4 * (size_t)B, 256);                  // base_slot
+        n += align_up(4, 256);                              // wide-cost flag
         if (p.nsplit > 1) {   // the blocks' sums over mission chunks
             const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
             n += align_up(4 * np, 256) + align_up(8 * np, 256);
@@ -2799,6 +2869,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.base_slot = nullptr;
     d.mm_cost = nullptr;
     d.mm_id = nullptr;
+    d.wide = nullptr;
     if (p.sparse) {
         const size_t lst = (size_t)p.ngroups * kSparseW * Mp;
         const size_t head = (size_t)p.ngroups * kSparseHead * Mp;
@@ -2807,6 +2878,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
         d.mm_cost = (int32_t *)take(4 * lst);
         d.mm_id = (unsigned char *)take(lst);
         d.base_slot = (int32_t *)take(4 * (size_t)B);
+        d.wide = (int32_t *)take(4);
         if (p.nsplit > 1) {
             const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
             d.part_cov = (int32_t *)take(4 * np);
@@ -2918,7 +2990,7 @@ fs_status sweep_rows(const EngineTables &t, const EngineConfig &c, int32_t step,
 }
 }  // namespace
 
-fs_status engine_sparse_prepare(const EngineTables &t, hipStream_t s)
+fs_status engine_sparse_prepare(const EngineTables &t, EngineConfig &c, hipStream_t s)
 {
     // (one instance: the descriptor's plan gives the grid of the list build)
     InstDesc d;
@@ -2926,8 +2998,21 @@ fs_status engine_sparse_prepare(const EngineTables &t, hipStream_t s)
     FS_HIP(hipStreamSynchronize(s));
     if (!d.sparse) return fail(FS_E_INTERNAL, "sparse preparation of a dense plan");
     const int grid = d.ngroups * ((d.Mp + 63) / 64);
-    k_sparse_build<<<grid, kBlock, 0, s>>>(t.desc);
-    FS_HIP(hipGetLastError());
+    // packed lists unless some cost does not fit a key (then built again)
+    c.sparse_packed = false;
+    if (env_int("FS_SPARSE_PACKED", 1) != 0) {
+        FS_TRY(engine_fill_i32(d.wide, 1, 0, s));
+        k_sparse_build<true><<<grid, kBlock, 0, s>>>(t.desc);
+        FS_HIP(hipGetLastError());
+        int32_t wide = 1;
+        FS_HIP(hipMemcpyAsync(&wide, d.wide, sizeof wide, hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+        c.sparse_packed = wide == 0;
+    }
+    if (!c.sparse_packed) {
+        k_sparse_build<false><<<grid, kBlock, 0, s>>>(t.desc);
+        FS_HIP(hipGetLastError());
+    }
     k_sparse_slots<<<std::max(1, std::min(64, (d.B + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
         t.desc);
     FS_HIP(hipGetLastError());
@@ -2945,8 +3030,10 @@ fs_status sweep_sparse(const EngineTables &t, const EngineConfig &c, int32_t ste
     const uint32_t lds = (uint32_t)sweep_lds_bytes(kSparseW, c.Kmax);
     {
         TimedLaunch tm(0);
-        launch_timed(k_sweep_sparse<kWideBlock>, dim3(t.nsweep), dim3(kWideBlock), lds, s,
-                     tm.start(), tm.stop(), t.desc, t.single ? nullptr : t.sweep, step);
+        launch_timed(c.sparse_packed ? k_sweep_sparse<kWideBlock, true>
+                                     : k_sweep_sparse<kWideBlock, false>,
+                     dim3(t.nsweep), dim3(kWideBlock), lds, s, tm.start(), tm.stop(), t.desc,
+                     t.single ? nullptr : t.sweep, step);
         FS_HIP(hipGetLastError());
         tm.used();
     }

@@ -386,7 +386,7 @@ fs_status run_launch_set(LaunchSet &ls, int32_t N, hipStream_t s)
     if (ls.any_rank) FS_TRY(engine_rank_lists(ls.tabs, ls.rank_rows, ls.nrank_rows, ls.Bmax, s));
     if (ls.any_typed) FS_TRY(engine_fleet_lists(ls.tabs, s));
     FS_TRY(engine_init(ls.tabs, ls.cfg, 0, s));
-    if (ls.cfg.sparse && N >= 1) FS_TRY(engine_sparse_prepare(ls.tabs, s));
+    if (ls.cfg.sparse && N >= 1) FS_TRY(engine_sparse_prepare(ls.tabs, ls.cfg, s));
     if (ls.cfg.persistent) return N >= 1 ? engine_persistent(ls.tabs, ls.cfg, s) : FS_OK;
     if (N >= 1) FS_TRY(tune_sweep(ls, s));
     for (int32_t t = 1; t <= N; ++t) {

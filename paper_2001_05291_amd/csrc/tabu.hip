@@ -50,7 +50,7 @@ extern "C" fs_status fs_move_scores(const int32_t *C, int64_t ldc, int32_t B, in
     FS_TRY(build_launch_set({sp}, env_int("FS_SWEEP_TARGET_WG", 256), ls, s));
     FS_TRY(engine_reset(ls.tabs, ls.Bmax, ls.cfg.Kmax, s));
     FS_TRY(engine_init(ls.tabs, ls.cfg, 0, s));
-    if (ls.cfg.sparse) FS_TRY(engine_sparse_prepare(ls.tabs, s));
+    if (ls.cfg.sparse) FS_TRY(engine_sparse_prepare(ls.tabs, ls.cfg, s));
     FS_TRY(engine_sweep(ls.tabs, ls.cfg, 1, s));
     FS_HIP(hipStreamSynchronize(s));
     return FS_OK;

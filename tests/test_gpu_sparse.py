@@ -164,6 +164,33 @@ def test_tabu_trace_wide_costs():
     assert_same(g, o, C, 2**30)
 
 
+@pytest.mark.parametrize("packed", [0, 1])
+def test_packed_lists_at_the_key_boundary(packed):
+    # lists packed into (cost << 6 | id) keys when every cost is below
+    # 2^26 - 1, unpacked otherwise: costs just below the boundary (packed),
+    # one cost on it (built again unpacked), and the second-nearest cost at
+    # and beyond it (thresholds of the packed walk); also ordinary tables with
+    # packing switched off
+    top = 2**26 - 1
+    rng = np.random.default_rng(52 + packed)
+    tables = []
+    C = rng.integers(top - 40, top, size=(130, 300)).astype(np.int32)
+    tables.append((C, top - 20))
+    C2 = C.copy()
+    C2[77, 123] = top
+    tables.append((C2, top))
+    C3 = rng.integers(1, 60, size=(130, 300)).astype(np.int32)
+    C3[:, ::7] = top - 1
+    tables.append((C3, 2**31 - 2))
+    tables.append((rng.integers(1, 5000, size=(97, 401)).astype(np.int32), 4000))
+    for C, R in tables:
+        with env(FS_SPARSE_PACKED=packed):
+            g, o = run_both(C, 11, R, 4, 30, ldc=C.shape[1] + 3, split=2)
+        assert_same(g, o, C, R)
+        with env(FS_SPARSE_PACKED=packed):
+            check_scores(C, rng.choice(C.shape[0], 11, replace=False).tolist(), R, split=3)
+
+
 def test_default_rule_picks_sparse_for_many_closed_bases():
     """Many closed bases and a long search take the sparse sweep by default
     (its block scoring shows up as the "finalize" timing group); the result
