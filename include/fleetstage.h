@@ -131,10 +131,11 @@ fs_status fs_build_cost_table(const double *base_latlon_deg, int32_t B,
  * hospitals): hosp_latlon_deg (device, H x 2 degrees) and mission_ph
  * (device, M x 2 int32: pickup and delivery hospital ids).  Mission m's
  * coordinates are those of its two hospitals, and the result is bitwise the
- * direct form's for those coordinates (each leg is the same haversine call
- * and the legs are summed in the same order), computed with 2 B H + M
- * haversines instead of 2 B M.  1 <= H <= 10,000 (two FP64 legs per hospital
- * are staged on chip); FS_E_INVALID for ids outside [0, H) (after a check on
+ * direct form's for those coordinates (each leg is the same haversine,
+ * which is symmetric bit for bit, and the legs are summed in the same
+ * order), computed with B H + M haversines instead of 2 B M.
+ * 1 <= H <= 16,384 (one FP64 leg per hospital is staged on chip);
+ * FS_E_INVALID for ids outside [0, H) (after a check on
  * the device; nothing is written then) and for the checks of
  * fs_build_cost_table.  Synchronises the stream once (the id check). */
 fs_status fs_build_cost_table_indexed(const double *base_latlon_deg, int32_t B,

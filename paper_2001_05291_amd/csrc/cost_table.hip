@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_cost_columns(const double *__restric
 // same doubles as the direct form's mission coordinates) and a check of the
 // ids (bad ids are counted, and the table is not built).
 constexpr int kIndexedBlock = 1024;
-constexpr int32_t kIndexedMaxH = 10000;   // two FP64 legs per hospital in LDS
+constexpr int32_t kIndexedMaxH = 16384;   // one FP64 leg per hospital in LDS (128 KB)
 
 __global__ __launch_bounds__(kBlock) void k_mission_legs(const double *__restrict__ hosp,
                                                          int32_t H,
@@ -149,18 +149,19 @@ __global__ __launch_bounds__(kBlock) void k_mission_legs(const double *__restric
     packed[m] = (uint32_t)p | ((uint32_t)d << 16);
 }
 
-// One workgroup per base: the legs base -> hospital and hospital -> base for
-// every hospital in LDS (the direct form's two haversine calls with the same
-// arguments), then C[b][m] = (leg(b, p) + pd) + leg(d, b) for every mission,
-// in the direct form's order, so the table is bitwise the direct form's.
+// One workgroup per base: the leg between the base and every hospital in LDS,
+// then C[b][m] = (leg(b, p) + pd) + leg(d, b) for every mission, in the
+// direct form's order.  The haversine above is symmetric bit for bit (the
+// two angle differences only change sign, sin is odd, and the product of
+// the cosines commutes), so one leg per hospital serves both directions and
+// the table is bitwise the direct form's (tested).
 __global__ __launch_bounds__(kIndexedBlock) void k_cost_indexed(
     const double *__restrict__ bases, const double *__restrict__ hosp, int32_t H,
     const double *__restrict__ pd, const uint32_t *__restrict__ packed, int32_t M, double two_r,
     int32_t legs, int32_t *__restrict__ C, double *__restrict__ Cf, int64_t ldc)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double *to_h = reinterpret_cast<double *>(smem);   // base -> hospital
-    double *from_h = to_h + H;                         // hospital -> base
+    double *leg = reinterpret_cast<double *>(smem);   // base <-> hospital
     const int32_t b = blockIdx.x;
     const double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
     const double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
@@ -169,15 +170,14 @@ __global__ __launch_bounds__(kIndexedBlock) void k_cost_indexed(
         const double phi_h = hosp[2 * (int64_t)h] * kDeg2Rad;
         const double psi_h = hosp[2 * (int64_t)h + 1] * kDeg2Rad;
         const double cos_h = cos(phi_h);
-        to_h[h] = haversine(phi_b, psi_b, cos_b, phi_h, psi_h, cos_h, two_r);
-        from_h[h] = haversine(phi_h, psi_h, cos_h, phi_b, psi_b, cos_b, two_r);
+        leg[h] = haversine(phi_b, psi_b, cos_b, phi_h, psi_h, cos_h, two_r);
     }
     __syncthreads();
     const int64_t row = (int64_t)b * ldc;
     for (int32_t m = threadIdx.x; m < M; m += kIndexedBlock) {
         const uint32_t q = packed[m];
-        const double bp = to_h[q & 0xFFFF];
-        const double db = from_h[q >> 16];
+        const double bp = leg[q & 0xFFFF];
+        const double db = leg[q >> 16];
         const double v = (legs == 3) ? (bp + pd[m]) + db : bp + db;
         C[row + m] = (int32_t)rint(v);
         if (Cf) Cf[row + m] = v;
@@ -276,7 +276,7 @@ extern "C" fs_status fs_build_cost_table_indexed(const double *base_latlon_deg, 
     if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && nbad == 0) {
-        const size_t lds = 2 * sizeof(double) * (size_t)H;
+        const size_t lds = sizeof(double) * (size_t)H;
         e = hipFuncSetAttribute((const void *)k_cost_indexed,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess) {

@@ -42,6 +42,7 @@ struct InstDesc {
     // cost (the lists are then built again unpacked)
     int32_t *wide;
     int32_t *base_slot;      // B: closed slot (>= 0) or -1 - open slot
+    int32_t *base_tabu;      // B: tabu expiry by base id (sparse sweep: loaded with the slot)
     int32_t nclosed, chunk, nsplit, ngroups;
     int32_t active;          // 0: every kernel skips this instance
     int32_t start_step;      // launch step at which this instance's iteration 0 ends

@@ -757,6 +757,8 @@ __global__ __launch_bounds__(BS) void k_refresh(const InstDesc *__restrict__ des
                 if (d.sparse) {
                     d.base_slot[best.j_base] = -1 - i_slot;
                     d.base_slot[best.i_base] = j_slot;
+                    d.base_tabu[best.j_base] = t + d.T;
+                    d.base_tabu[best.i_base] = t + d.T;
                 }
                 if (TY && d.typed) {   // the base kinds trade list slots with the bases
                     const int32_t h = d.open_hel[i_slot];
@@ -1755,14 +1757,20 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     }
 }
 
-// base_slot from the open and closed lists (before the first sparse sweep).
+// base_slot and base_tabu from the open and closed lists and their expiries
+// (before the first sparse sweep).
 __global__ __launch_bounds__(kBlock) void k_sparse_slots(const InstDesc *__restrict__ descs)
 {
     const InstDesc &d = descs[0];
-    for (int32_t js = threadIdx.x + blockIdx.x * kBlock; js < d.nclosed; js += gridDim.x * kBlock)
+    for (int32_t js = threadIdx.x + blockIdx.x * kBlock; js < d.nclosed;
+         js += gridDim.x * kBlock) {
         d.base_slot[d.closed[js]] = js;
-    for (int32_t k = threadIdx.x + blockIdx.x * kBlock; k < d.K; k += gridDim.x * kBlock)
+        d.base_tabu[d.closed[js]] = d.closed_tabu[js];
+    }
+    for (int32_t k = threadIdx.x + blockIdx.x * kBlock; k < d.K; k += gridDim.x * kBlock) {
         d.base_slot[d.open[k]] = -1 - k;
+        d.base_tabu[d.open[k]] = d.open_tabu[k];
+    }
 }
 
 // The dense visit's terms for one element c < b2 of a row, added to the
@@ -1799,7 +1807,9 @@ __device__ __forceinline__ void sparse_rows(const InstDesc &d, int32_t q, bool w
 {
     const int lane = threadIdx.x & 63;
     const int32_t b = q * kSparseW + lane;
+    // (slot and expiry by base id: one round of loads)
     const int32_t slot = b < d.B ? d.base_slot[b] : -1;
+    const int32_t tabu = b < d.B && with_tabu ? d.base_tabu[b] : 0;
     const bool closed = slot >= 0;
     const u64 mask = __builtin_amdgcn_ballot_w64(closed);
     const int32_t row = (int32_t)__builtin_popcountll(mask & ((1ull << lane) - 1));
@@ -1807,7 +1817,7 @@ __device__ __forceinline__ void sparse_rows(const InstDesc &d, int32_t q, bool w
     if (closed) {
         s_jrow[row] = b;
         s_jslot[row] = slot;
-        s_jtabu[row] = with_tabu ? d.closed_tabu[slot] : 0;
+        s_jtabu[row] = tabu;
         s_jhel[row] = 0;
     }
     if (lane == 0) *s_nrows = (int32_t)__builtin_popcountll(mask);
@@ -2820,7 +2830,7 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
         const size_t head = (size_t)p.ngroups * kSparseHead * Mp;
         n += align_up(4 * head, 256) + align_up(head, 256);   // sorted heads: costs, ids
         n += align_up(4 * lst, 256) + align_up(lst, 256);     // sorted lists: costs, ids
-        n += align_up(4 * (size_t)B, 256);                  // base_slot
+        n += 2 * align_up(4 * (size_t)B, 256);              // base_slot, base_tabu
         n += align_up(4, 256);                              // wide-cost flag
         if (p.nsplit > 1) {   // the blocks' sums over mission chunks
             const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);
@@ -2867,6 +2877,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.lst_cost = nullptr;
     d.lst_id = nullptr;
     d.base_slot = nullptr;
+    d.base_tabu = nullptr;
     d.mm_cost = nullptr;
     d.mm_id = nullptr;
     d.wide = nullptr;
@@ -2878,6 +2889,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
         d.mm_cost = (int32_t *)take(4 * lst);
         d.mm_id = (unsigned char *)take(lst);
         d.base_slot = (int32_t *)take(4 * (size_t)B);
+        d.base_tabu = (int32_t *)take(4 * (size_t)B);
         d.wide = (int32_t *)take(4);
         if (p.nsplit > 1) {
             const size_t np = (size_t)p.ngroups * kSparseW * (K + 1);

@@ -172,12 +172,20 @@ def read_valu(path: str, workload: str):
     return float(kv["valu_lane_ops_per_launch"])
 
 
-def sparse_sweep_bytes(C, open_ids, width: int = 64) -> int:
+def sparse_entry_bytes(C) -> int:
+    """Bytes per sorted-list entry: a packed 32-bit (cost << 6 | id) key when
+    every cost is below 2^26 - 1, else an int32 cost and a uint8 id."""
+    import numpy as np
+    return 4 if int(np.asarray(C).max()) < (1 << 26) - 1 else 5
+
+
+def sparse_sweep_bytes(C, open_ids, width: int = 64, entry_bytes: int | None = None) -> int:
     """Bytes the sparse sweep needs in one iteration at placement open_ids:
     for every block of `width` base ids and every mission, the block's sorted
     list up to and including the first entry not below the mission's
-    second-nearest open cost (5 B per entry: int32 cost + uint8 id), plus the
-    mission's state (b1, b2, o1: 12 B) once per block.  C: host (B, M) int32."""
+    second-nearest open cost (entry_bytes per entry: 4 packed, 5 unpacked;
+    by default what the table allows), plus the mission's state (b1, b2, o1:
+    12 B) once per block.  C: host (B, M) int32."""
     import numpy as np
     C = np.asarray(C)
     B, M = C.shape
@@ -192,7 +200,9 @@ def sparse_sweep_bytes(C, open_ids, width: int = 64) -> int:
         blk = C[q * width:min(B, (q + 1) * width)]
         below = (blk.astype(np.int64) < b2[None, :]).sum(axis=0)
         entries += int(np.minimum(below + 1, width).sum())
-    return entries * 5 + nb * M * 12
+    if entry_bytes is None:
+        entry_bytes = sparse_entry_bytes(C)
+    return entries * entry_bytes + nb * M * 12
 
 
 def read_traffic(path: str, workload: str):

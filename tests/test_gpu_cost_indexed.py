@@ -51,7 +51,7 @@ def test_bitwise_equal_to_direct_form_and_oracle(name):
 
 
 def test_two_legs_pitch_and_many_hospitals():
-    inst = synth.make_instance(seed=61, B=37, H=10_000, M=2003)
+    inst = synth.make_instance(seed=61, B=37, H=16_384, M=2003)
     for legs, ldc in ((3, 2008), (2, 2003)):
         (Cd, Cfd), (Ci, Cfi) = both(inst, legs=legs, ldc=ldc)
         assert np.array_equal(Ci, Cd)
@@ -65,7 +65,7 @@ def test_bad_ids_and_too_many_hospitals_are_errors():
     with pytest.raises(fs.FleetstageError) as e:
         fs.build_cost_table_indexed(to_dev(inst.bases), to_dev(inst.hospitals), to_dev(ph))
     assert e.value.status == fs.FS_E_INVALID
-    big = np.zeros((10_001, 2))
+    big = np.zeros((16_385, 2))
     with pytest.raises(fs.FleetstageError) as e:
         fs.build_cost_table_indexed(to_dev(inst.bases), to_dev(big), to_dev(inst.mission_ph))
     assert e.value.status == fs.FS_E_INVALID
