@@ -398,8 +398,10 @@ fs_status fs_serve_close(fs_server *sv);
  * several microseconds, so sampling keeps the timed loop close to its untimed
  * pace); on = 0 disables, a negative value is FS_E_INVALID; groups are
  * "sweep" (move evaluation, including the chunk-merge kernel when the mission
- * axis is split) and "refresh" (argmax, move application and the open-base
- * state of the new placement); "finalize" is accepted and stays empty.
+ * axis is split), "refresh" (argmax, move application and the open-base
+ * state of the new placement), "finalize" (the sparse sweep's block scoring
+ * when it runs as a kernel of its own) and "score_refresh" (that scoring and
+ * the refresh in one launch).
  * Enabling or disabling discards what was recorded.  Process-wide; not meant
  * for concurrent solves. */
 fs_status fs_timing_enable(int32_t on);

@@ -44,6 +44,8 @@ struct InstDesc {
     int32_t *base_slot;      // B: closed slot (>= 0) or -1 - open slot
     int32_t *base_tabu;      // B: tabu expiry by base id (sparse sweep: loaded with the slot)
     int32_t nclosed, chunk, nsplit, ngroups;
+    int32_t ncand;           // row-group candidates the refresh reduces (sparse with
+                             // mission chunks: kScoreParts per base block)
     int32_t active;          // 0: every kernel skips this instance
     int32_t start_step;      // launch step at which this instance's iteration 0 ends
     int32_t *open;           // K      slot -> base id
@@ -101,6 +103,7 @@ struct InstPlan {
 constexpr int kSparseW = 64;   // bases per block of the sparse sweep (one wave)
 constexpr int kSparseHead = 4; // ranks of each sorted list also stored rank-major
 constexpr int kSparseMaxK = 64;
+constexpr int kScoreParts = 4;   // workgroups scoring one base block (16 rows each)
 // Plan of the sparse sweep: blocks of kSparseW bases x mission chunks.
 InstPlan plan_sparse(int32_t B, int32_t M, int32_t K, int target_wg);
 
@@ -126,6 +129,9 @@ struct EngineConfig {
     int Kmax = 1;
     bool sparse = false;   // the sparse sweep (single homogeneous instance)
     bool sparse_packed = false;   // its lists hold packed 32-bit keys
+    // the sparse sweep's block scoring and the refresh in one launch
+    // (k_score_refresh; one instance with mission chunks)
+    bool fuse_score = false;
     // persistent search: one workgroup per instance runs all N iterations
     // (k_solo); solo_lds is its dynamic LDS, sized for the largest instance
     bool persistent = false;

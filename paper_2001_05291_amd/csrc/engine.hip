@@ -626,16 +626,32 @@ __device__ void write_record(const InstDesc &d, int32_t t, const SolveState &s, 
 // added with integer atomics into one of kStripes accumulator copies (exact in
 // any order).  TY: the launch set holds a typed fleet (vehicle types per slot,
 // rotary-only missions, base kinds travelling with the swapped bases).
+// (refresh_tile: the work of one refresh workgroup; bid is its index among
+// the refresh workgroups (accumulator stripe); wait: block-scoring workgroups
+// of the same launch write the candidates (fused launch), whose completion is
+// awaited first.)
+constexpr int32_t kScoreWaitPolls = 1 << 22;   // bound of that wait (tens of ms)
+
+template <int MPT, bool TY, int BS>
+__device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs, const Tile tl,
+                                             int32_t step, int32_t bid, bool wait);
+
 template <int MPT, bool TY, int BS = kBlock>
 __global__ __launch_bounds__(BS) void k_refresh(const InstDesc *__restrict__ descs,
                                                 const Tile *__restrict__ tiles, int32_t step)
+{
+    refresh_tile<MPT, TY, BS>(descs, group_tile(tiles), step, (int32_t)blockIdx.x, false);
+}
+
+template <int MPT, bool TY, int BS>
+__device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs, const Tile tl,
+                                             int32_t step, int32_t bid, bool wait)
 {
     // BS == kWideBlock: MPT = 256 missions as four tiles of 64, each with four
     // waves splitting the open slots (a quarter of the workgroups of the
     // 64-mission form, each reducing the candidates once for 256 missions)
     static_assert(BS == kBlock || (BS == kWideBlock && MPT == 4 * kRefreshMissions),
                   "refresh geometry");
-    const Tile tl = group_tile(tiles);
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
@@ -655,10 +671,41 @@ __global__ __launch_bounds__(BS) void k_refresh(const InstDesc *__restrict__ des
     __shared__ int32_t s_improved;
 
     if (t >= 1) {
+        if (wait) {
+            // the block scores of this launch: every scoring workgroup adds 1
+            // (release, device scope) after its candidate; the bound turns a
+            // wait that never ends into a reported error
+            __shared__ int32_t s_go;
+            if (threadIdx.x == 0) {
+                int32_t go = 1;
+                if (!gptr(st)->stopped) {
+                    const int32_t target = d.ncand * t;
+                    int32_t polls = 0;
+                    // (relaxed polls, one acquire fence after: the caches are
+                    // invalidated once, not on every poll)
+                    while (__hip_atomic_load(&st->score_done, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < target) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++polls > kScoreWaitPolls) {
+                            go = 0;
+                            break;
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+                s_go = go;
+                if (!go && tl.g == 0 && !st->error) {
+                    st->error = 1;
+                    st->err_iter = t;
+                }
+            }
+            __syncthreads();
+            if (!s_go) return;
+        }
         // The stop flag, this thread's first candidates and its open slot go
         // out together and are waited for once.  (No closed base: no row
         // group and no move; the candidate array always holds one entry.)
-        const int32_t ncand = d.ngroups;
+        const int32_t ncand = d.ncand;
         const int32_t stopped = gptr(st)->stopped;
         constexpr int CU = BS == kBlock ? 4 : 1;
         const int32_t qlast = ncand > 0 ? ncand - 1 : 0;
@@ -910,7 +957,7 @@ __global__ __launch_bounds__(BS) void k_refresh(const InstDesc *__restrict__ des
         }
     }
     __syncthreads();
-    Acc *acc = d.acc[(t + 1) & 1] + (blockIdx.x & (kStripes - 1)) * (K + 1);
+    Acc *acc = d.acc[(t + 1) & 1] + (bid & (kStripes - 1)) * (K + 1);
     for (int k = threadIdx.x; k <= K; k += BS) {
         const u64 c = s_cov[k], dd = s_dist[k];
         if (c | dd) {
@@ -2043,14 +2090,30 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
 #undef FS_SPARSE_STEP
 #undef FS_SPARSE_KEY
 
-// Scores one base block from its sums over the mission chunks (added by the
-// sweep's chunks) and clears them for the next iteration (all kSparseW rows:
-// the next iteration's rows may differ).
+// Scores a quarter of one base block (16 of its closed rows, kScoreParts
+// workgroups per block) from the block's sums over the mission chunks (added
+// by the sweep's chunks) and clears them for the next iteration (all 16 row
+// slots: the next iteration's rows may differ).  Candidate kScoreParts * g + part.
+// (score_part: the work of one scoring workgroup; signal: the refresh
+// workgroups of the same launch wait for it, see refresh_tile.)
+template <int BS>
+__device__ __forceinline__ void score_part(const InstDesc *__restrict__ descs, const Tile tl,
+                                           int32_t step, bool signal);
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_score_sparse(const InstDesc *__restrict__ descs,
                                                      const Tile *__restrict__ tiles, int32_t step)
 {
-    const Tile tl = group_tile(tiles);
+    const Tile tl = tiles ? tiles[blockIdx.x]
+                          : Tile{0, (int32_t)blockIdx.x / kScoreParts,
+                                 (int32_t)blockIdx.x % kScoreParts, 0};
+    score_part<BS>(descs, tl, step, false);
+}
+
+template <int BS>
+__device__ __forceinline__ void score_part(const InstDesc *__restrict__ descs, const Tile tl,
+                                           int32_t step, bool signal)
+{
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
     const int32_t t = step - d.start_step;
@@ -2058,40 +2121,41 @@ __global__ __launch_bounds__(BS) void k_score_sparse(const InstDesc *__restrict_
     const SolveState st = *d.st;
     if (st.stopped) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int32_t K = d.K, K1 = K + 1;
-    const SweepLds L = carve_lds(smem, kSparseW, K);
+    constexpr int RP = kSparseW / kScoreParts;   // rows per part
+    const int32_t K = d.K, K1 = K + 1, part = tl.sp, r0 = part * RP;
+    const SweepLds L = carve_lds(smem, RP, K);
     __shared__ int32_t s_jrow[kSparseW], s_jslot[kSparseW], s_jtabu[kSparseW],
         s_jhel[kSparseW], s_rowof[kSparseW];
-    __shared__ int32_t s_t1c[kSparseW];
-    __shared__ int64_t s_t1d[kSparseW];
+    __shared__ int32_t s_t1c[RP];
+    __shared__ int64_t s_t1d[RP];
     __shared__ int32_t s_nrows;
     __shared__ Candidate s_red[BS / 64 + 1];
-    // the block's sums go out with the row and slot loads and are waited for
+    // this part's sums go out with the row and slot loads and are waited for
     // once
-    constexpr int PER = (kSparseW * (kSparseMaxK + 1) + BS - 1) / BS;
-    const int64_t base = (int64_t)tl.g * kSparseW * K1;
+    constexpr int PER = (RP * (kSparseMaxK + 1) + BS - 1) / BS;
+    const int64_t base = ((int64_t)tl.g * kSparseW + r0) * K1;
     int32_t pcv[PER];
     int64_t pdv[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int32_t idx = threadIdx.x + i * BS;
-        pcv[i] = idx < kSparseW * K1 ? d.part_cov[base + idx] : 0;
-        pdv[i] = idx < kSparseW * K1 ? d.part_dist[base + idx] : 0;
+        pcv[i] = idx < RP * K1 ? d.part_cov[base + idx] : 0;
+        pdv[i] = idx < RP * K1 ? d.part_dist[base + idx] : 0;
     }
     if (threadIdx.x < kSparseW)
         sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
     load_slot_inputs(d, t, L, false);
     __syncthreads();
-    const int32_t nrows = s_nrows;
+    const int32_t nr = min(max(s_nrows - r0, 0), RP);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int32_t idx = threadIdx.x + i * BS;
-        if (idx >= kSparseW * K1) continue;
+        if (idx >= RP * K1) continue;
         const int32_t c = pcv[i];
         const int64_t dd = pdv[i];
         d.part_cov[base + idx] = 0;
         d.part_dist[base + idx] = 0;
-        if (idx >= nrows * K1) continue;
+        if (idx >= nr * K1) continue;
         const int32_t r = idx / K1, k = idx - r * K1;
         if (k == 0) {
             s_t1c[r] = c;
@@ -2102,8 +2166,28 @@ __global__ __launch_bounds__(BS) void k_score_sparse(const InstDesc *__restrict_
         }
     }
     __syncthreads();
-    score_group<BS>(d, st, nrows, 1, t, tl.g, s_jrow, s_jtabu, s_jhel, L, s_t1c, s_t1d, s_red,
-                    s_jslot);
+    score_group<BS>(d, st, nr, 1, t, kScoreParts * tl.g + part, s_jrow + r0, s_jtabu + r0,
+                    s_jhel + r0, L, s_t1c, s_t1d, s_red, s_jslot + r0);
+    // (thread 0 wrote the candidate; its release publishes it)
+    if (signal && threadIdx.x == 0)
+        __hip_atomic_fetch_add(&d.st->score_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The block scores and the refresh of one iteration of the sparse sweep in
+// one launch (one instance): workgroups [0, nscore) score base-block parts and
+// never wait; the others are refresh workgroups, which wait for every
+// scoring workgroup's candidate (they are dispatched after them, so the wait
+// always ends) and then refresh as usual.  Saves a launch per iteration and
+// overlaps the refresh workgroups' start with the scoring.
+template <int MPT, bool TY, int BS>
+__global__ __launch_bounds__(BS) void k_score_refresh(const InstDesc *__restrict__ descs,
+                                                      int32_t nscore, int32_t step)
+{
+    const int32_t b = (int32_t)blockIdx.x;
+    if (b < nscore)
+        score_part<BS>(descs, Tile{0, b / kScoreParts, b % kScoreParts, 0}, step, true);
+    else
+        refresh_tile<MPT, TY, BS>(descs, Tile{0, b - nscore, 0, 0}, step, b - nscore, true);
 }
 
 // Sums the chunk partials of one row group of a split instance and scores it.
@@ -2822,7 +2906,7 @@ size_t instance_bytes(int32_t B, int32_t M, int32_t K, const InstPlan &p)
     n += align_up(4 * (size_t)B, 256);                          // typed ranking order
     n += 3 * align_up(4 * Mp, 256);                             // b1 b2 o1
     n += 2 * align_up(sizeof(Acc) * kStripes * (K + 1), 256);   // accumulators
-    n += align_up(sizeof(Candidate) * std::max(p.ngroups, 1), 256);
+    n += align_up(sizeof(Candidate) * std::max(p.ngroups * kScoreParts, 1), 256);
     n += align_up(sizeof(SolveState), 256);
     n += 2 * align_up(4 * (size_t)K, 256);                      // best_open, best_sorted
     if (p.sparse) {
@@ -2867,7 +2951,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.o1 = (int32_t *)take(4 * Mp);
     d.acc[0] = (Acc *)take(sizeof(Acc) * kStripes * (K + 1));
     d.acc[1] = (Acc *)take(sizeof(Acc) * kStripes * (K + 1));
-    d.cand = (Candidate *)take(sizeof(Candidate) * std::max(p.ngroups, 1));
+    d.cand = (Candidate *)take(sizeof(Candidate) * std::max(p.ngroups * kScoreParts, 1));
     d.st = (SolveState *)take(sizeof(SolveState));
     d.best_open = (int32_t *)take(4 * (size_t)K);
     d.best_sorted = (int32_t *)take(4 * (size_t)K);
@@ -2907,6 +2991,7 @@ void carve_instance(InstDesc &d, char *base, int32_t B, int32_t M, int32_t K, co
     d.K = K;
     d.nclosed = p.nclosed;
     d.ngroups = p.ngroups;
+    d.ncand = p.sparse && p.nsplit > 1 ? p.ngroups * kScoreParts : p.ngroups;
     d.nsplit = p.nsplit;
     d.chunk = p.chunk;
 }
@@ -2924,7 +3009,9 @@ void build_tiles(const std::vector<InstPlan> &plans, const std::vector<int32_t> 
         for (int32_t g = 0; g < ng; ++g)
             for (int32_t sp = 0; sp < p.nsplit; ++sp) sweep.push_back(Tile{(int32_t)i, g, sp, 0});
         if (p.nsplit > 1)
-            for (int32_t g = 0; g < p.ngroups; ++g) score.push_back(Tile{(int32_t)i, g, 0, 0});
+            for (int32_t g = 0; g < p.ngroups; ++g)
+                for (int32_t part = 0; part < (p.sparse ? kScoreParts : 1); ++part)
+                    score.push_back(Tile{(int32_t)i, g, part, 0});
         const int32_t nt = (Mp[i] + refresh_mpt - 1) / refresh_mpt;
         for (int32_t g = 0; g < nt; ++g) refresh.push_back(Tile{(int32_t)i, g, 0, 0});
     }
@@ -3049,9 +3136,10 @@ fs_status sweep_sparse(const EngineTables &t, const EngineConfig &c, int32_t ste
         FS_HIP(hipGetLastError());
         tm.used();
     }
-    if (t.nscore > 0) {   // (timed apart, as the "finalize" group)
+    if (t.nscore > 0 && !c.fuse_score) {   // (timed apart, as the "finalize" group)
         TimedLaunch tm(2);
-        launch_timed(k_score_sparse<kWideBlock>, dim3(t.nscore), dim3(kWideBlock), lds, s,
+        launch_timed(k_score_sparse<kBlock>, dim3(t.nscore), dim3(kBlock),
+                     (uint32_t)sweep_lds_bytes(kSparseW / kScoreParts, c.Kmax), s,
                      tm.start(), tm.stop(), t.desc, t.single ? nullptr : t.score, step);
         FS_HIP(hipGetLastError());
         tm.used();
@@ -3084,6 +3172,22 @@ fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t ste
 fs_status engine_refresh(const EngineTables &t, const EngineConfig &c, int32_t step, hipStream_t s)
 {
     if (t.nrefresh == 0) return FS_OK;
+    if (c.fuse_score && t.nscore > 0) {
+        // the block scores and the refresh in one launch (timed as "score_refresh")
+        typedef void (*Fused)(const InstDesc *, int32_t, int32_t);
+        Fused k = c.refresh_wide ? k_score_refresh<kBlock, false, kWideBlock>
+                  : c.refresh_mpt == kBlock ? k_score_refresh<kBlock, false, kBlock>
+                                            : k_score_refresh<kRefreshMissions, false, kBlock>;
+        const uint32_t lds =
+            (uint32_t)std::max(refresh_lds_bytes(c.Kmax),
+                               sweep_lds_bytes(kSparseW / kScoreParts, c.Kmax));
+        TimedLaunch timed(3);
+        launch_timed(k, dim3(t.nscore + t.nrefresh), dim3(c.refresh_wide ? kWideBlock : kBlock),
+                     lds, s, timed.start(), timed.stop(), t.desc, (int32_t)t.nscore, step);
+        FS_HIP(hipGetLastError());
+        timed.used();
+        return FS_OK;
+    }
     TimedLaunch timed(1);
     launch_timed(refresh_kernel(c), dim3(t.nrefresh), dim3(c.refresh_wide ? kWideBlock : kBlock),
                  (uint32_t)refresh_lds_bytes(c.Kmax), s, timed.start(), timed.stop(), t.desc,

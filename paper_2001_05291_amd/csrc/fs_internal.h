@@ -104,6 +104,9 @@ struct SolveState {
     int32_t err_iter;
     int32_t have_last;  // permuted searches: this pass has accepted a move ...
     uint64_t last_key;  // ... whose priority was last_key
+    int32_t score_done; // fused score + refresh launches: block-scoring workgroups
+                        // finished so far (each adds 1 after its candidate)
+    int32_t pad;
 };
 
 // Accumulator of the per-placement sums: slot 0 is G (the placement's value),

@@ -126,6 +126,14 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
                        env_int("FS_PERSIST_TAB", 1) != 0;
         cfg.solo_lds = (uint32_t)(cfg.solo_tab ? lds_tab : lds);
     }
+    // the sparse sweep's block scoring fused with the refresh (one instance
+    // with mission chunks; not for the full score table, which the sweep
+    // launch alone must produce).  Off by default: measured 38.8 us per fused
+    // launch against 10.9 + 12.9 us for the two launches at 3,936 closed rows
+    // x 100,000 missions (the release fences of 252 scoring workgroups and the
+    // waiting refresh workgroups cost more than the launch they save).
+    cfg.fuse_score = cfg.sparse && n == 1 && plans[0].nsplit > 1 && !specs[0].sc_cov &&
+                     env_int("FS_FUSE", 0) != 0;
     std::vector<Tile> solo;
     if (cfg.persistent) {
         // largest instances first, so that they do not finish last

@@ -25,8 +25,8 @@ struct Group {
 };
 std::mutex g_mu;
 int32_t g_period = 0;          // 0: off; n: time every n-th launch of each group
-int64_t g_count[3] = {0, 0, 0};
-Group g_groups[3];
+int64_t g_count[4] = {0, 0, 0, 0};
+Group g_groups[4];
 std::vector<hipEvent_t> g_free;
 
 constexpr size_t kKeepPending = 64;   // read back older pairs beyond this many
@@ -37,6 +37,7 @@ int group_index(const char *name)
     if (n == "sweep") return 0;
     if (n == "refresh") return 1;
     if (n == "finalize") return 2;
+    if (n == "score_refresh") return 3;
     return -1;
 }
 

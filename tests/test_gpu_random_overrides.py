@@ -22,7 +22,7 @@ fs = None
 
 KEYS = ("FS_SWEEP_J", "FS_SWEEP_U", "FS_SWEEP_QUEUE", "FS_SWEEP_WIDE", "FS_SWEEP_SPLIT",
         "FS_REFRESH_WIDE", "FS_REFRESH_SPLIT4", "FS_SPARSE", "FS_SPARSE_SPLIT", "FS_AUTOTUNE",
-        "FS_PERSIST", "FS_PERSIST_TAB", "FS_SPARSE_PACKED")
+        "FS_PERSIST", "FS_PERSIST_TAB", "FS_SPARSE_PACKED", "FS_FUSE")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -67,6 +67,8 @@ def draw_env(rng):
         env["FS_SPARSE_SPLIT"] = int(rng.integers(1, 4))
     if rng.random() < 0.3:
         env["FS_SPARSE_PACKED"] = int(rng.integers(0, 2))
+    if rng.random() < 0.3:
+        env["FS_FUSE"] = int(rng.integers(0, 2))
     env["FS_AUTOTUNE"] = int(rng.integers(0, 2))
     return env
 

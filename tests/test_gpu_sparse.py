@@ -191,10 +191,25 @@ def test_packed_lists_at_the_key_boundary(packed):
             check_scores(C, rng.choice(C.shape[0], 11, replace=False).tolist(), R, split=3)
 
 
+@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_fused_scoring_and_refresh(fuse, mode):
+    # the block scoring and the refresh in one launch (refresh workgroups wait
+    # for the scoring ones) or in two, with mission chunks and both refresh
+    # widths
+    inst = synth.make_instance(seed=53, B=300, H=500, M=6000)
+    C, _ = oracle.cost_table(inst.bases, inst.missions, want_cf=False)
+    for split, wide in ((4, 0), (3, 1)):
+        with env(FS_FUSE=fuse, FS_REFRESH_SPLIT4=wide):
+            g, o = run_both(C, 20, 1_000_000, 6, 50, mode=mode, seed=9, split=split)
+        assert_same(g, o, C, 1_000_000)
+
+
 def test_default_rule_picks_sparse_for_many_closed_bases():
     """Many closed bases and a long search take the sparse sweep by default
-    (its block scoring shows up as the "finalize" timing group); the result
-    equals the dense sweep's record for record."""
+    (its block scoring shows up as the "finalize" timing group, or fused with
+    the refresh as "score_refresh"); the result equals the dense sweep's
+    record for record."""
     inst = synth.make_instance(seed=48, B=2100, H=600, M=4000)   # 3 mission chunks
     C, _ = oracle.cost_table(inst.bases, inst.missions, want_cf=False)
     Cd = padded_table(C, 4000)
@@ -202,10 +217,11 @@ def test_default_rule_picks_sparse_for_many_closed_bases():
     a = fs.tabu_solve(Cd, 10, 900_000, 7, 100)
     torch.cuda.synchronize()
     _, fin = fs.timing_read("finalize")
+    _, fused = fs.timing_read("score_refresh")
     fs.timing_read("sweep")
     fs.timing_read("refresh")
     fs.timing_enable(False)
-    assert fin > 0
+    assert fin + fused > 0
     with env(FS_SPARSE=0):
         b = fs.tabu_solve(Cd, 10, 900_000, 7, 100)
     assert np.array_equal(a.best_open.cpu().numpy(), b.best_open.cpu().numpy())
