@@ -174,13 +174,27 @@ __global__ __launch_bounds__(kIndexedBlock) void k_cost_indexed(
     }
     __syncthreads();
     const int64_t row = (int64_t)b * ldc;
-    for (int32_t m = threadIdx.x; m < M; m += kIndexedBlock) {
-        const uint32_t q = packed[m];
-        const double bp = leg[q & 0xFFFF];
-        const double db = leg[q >> 16];
-        const double v = (legs == 3) ? (bp + pd[m]) + db : bp + db;
-        C[row + m] = (int32_t)rint(v);
-        if (Cf) Cf[row + m] = v;
+    // four missions per thread and step, their loads issued together
+    constexpr int U = 4;
+    for (int32_t m0 = threadIdx.x; m0 < M; m0 += U * kIndexedBlock) {
+        uint32_t q[U];
+        double pdm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t m = m0 + u * kIndexedBlock;
+            q[u] = m < M ? packed[m] : 0u;
+            pdm[u] = m < M ? pd[m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t m = m0 + u * kIndexedBlock;
+            if (m >= M) break;
+            const double bp = leg[q[u] & 0xFFFF];
+            const double db = leg[q[u] >> 16];
+            const double v = (legs == 3) ? (bp + pdm[u]) + db : bp + db;
+            C[row + m] = (int32_t)rint(v);
+            if (Cf) Cf[row + m] = v;
+        }
     }
 }
 
