@@ -1542,8 +1542,10 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     if (!d.active) return;
     const int32_t t = step - d.start_step;
     if (t < 1 || t > d.N) return;
+    // The search state, this group's rows and the slot inputs go out in one
+    // round of loads; the stop flag is checked once they are issued (before
+    // anything is written to device memory).
     const SolveState st = *d.st;
-    if (st.stopped) return;
     const bool scoring = d.nsplit == 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K;
@@ -1557,11 +1559,6 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     __shared__ int64_t s_sum_d[NC * J];
     __shared__ Candidate s_red[BS / 64 + 1];
 
-    if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
-    for (int q = threadIdx.x; q < J * K; q += BS) {
-        L.bd[q] = 0;
-        L.bc[q] = 0;
-    }
     const int32_t nclosed = d.nclosed;
     if (threadIdx.x < J) {
         const int32_t js = tl.g * J + threadIdx.x;
@@ -1573,6 +1570,12 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
         }
     }
     if (scoring) load_slot_inputs(d, t, L, NC == 2);
+    if (st.stopped) return;
+    if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
+    for (int q = threadIdx.x; q < J * K; q += BS) {
+        L.bd[q] = 0;
+        L.bc[q] = 0;
+    }
     __syncthreads();
 
     int32_t jrow[J];
@@ -1926,8 +1929,9 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
     if (!d.active) return;
     const int32_t t = step - d.start_step;
     if (t < 1 || t > d.N) return;
+    // (the search state, the block's rows and the slot inputs go out in one
+    // round of loads; the stop flag is checked once they are issued)
     const SolveState st = *d.st;
-    if (st.stopped) return;
     const bool scoring = d.nsplit == 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t K = d.K, R = d.R;
@@ -1940,17 +1944,18 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
     __shared__ Candidate s_red[BS / 64 + 1];
     __shared__ int32_t s_q[BS / 64][kSparseQ];
 
-    if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
-    for (int q = threadIdx.x; q < kSparseW * K; q += BS) {
-        L.bd[q] = 0;
-        L.bc[q] = 0;
-    }
     if (threadIdx.x < kSparseW) {
         s_t1c[threadIdx.x] = 0;
         s_t1d[threadIdx.x] = 0;
         sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
     }
     if (scoring) load_slot_inputs(d, t, L, false);
+    if (st.stopped) return;
+    if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
+    for (int q = threadIdx.x; q < kSparseW * K; q += BS) {
+        L.bd[q] = 0;
+        L.bc[q] = 0;
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
