@@ -53,6 +53,7 @@ typedef unsigned long long u64;
 // loads, counted by vmcnt alone, so waiting for an LDS result does not also
 // wait for them (generic loads count against both counters).
 typedef const __attribute__((address_space(1))) int32_t gi32;
+typedef const __attribute__((address_space(1))) v4i gv4i;
 template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p)
 {
@@ -79,6 +80,13 @@ __device__ __forceinline__ void gstore(T *p, const T &v)
     const int32_t *w = reinterpret_cast<const int32_t *>(&v);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(T) / 4); ++i) q[i] = w[i];
+}
+
+// Relaxed device-scope atomic add through a global view (no returned value).
+template <typename T>
+__device__ __forceinline__ void gatomic_add(T *p, T v)
+{
+    (void)__hip_atomic_fetch_add(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -226,10 +234,11 @@ __device__ __forceinline__ void acc_sum(const Acc *acc, int32_t K, int32_t k, in
                                         int64_t &dd)
 {
     u64 sc = 0, sd = 0;
+    const Acc *ga = acc;
 #pragma unroll
     for (int s = 0; s < kStripes; ++s) {
-        sc += acc[s * (K + 1) + k].cov;
-        sd += acc[s * (K + 1) + k].dist;
+        sc += ga[s * (K + 1) + k].cov;
+        sd += ga[s * (K + 1) + k].dist;
     }
     c = (int32_t)(int64_t)sc;
     dd = (int64_t)sd;
@@ -840,18 +849,19 @@ __device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs,
         // one mission per thread, every open slot in turn (small K)
         m = tl.g * MPT + threadIdx.x;
         owner = true;
-        kind = (TY && d.rho && m < M) ? (d.rho[m] != 0) : 0;
+        kind = (TY && d.rho && m < M) ? (gptr(d.rho)[m] != 0) : 0;
         if (m < M) {
-            const int32_t *col = d.C + m;
+            const gi32 *col = (const gi32 *)(d.C + m);
             constexpr int UNR = 16;
             for (int32_t k0 = 0; k0 < K; k0 += UNR) {
                 int32_t c[UNR], id[UNR];
+                bool ok[UNR];
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
                     const int32_t k = k0 + u;
-                    const bool ok = k < K && (!TY || !kind || s_rot[k]);
-                    id[u] = ok ? s_open[k] : 0;
-                    c[u] = ok ? col[(int64_t)id[u] * ldc] : INT32_MAX;
+                    ok[u] = k < K && (!TY || !kind || s_rot[k]);
+                    id[u] = ok[u] ? s_open[k] : 0;
+                    c[u] = ok[u] ? col[(int64_t)id[u] * ldc] : INT32_MAX;
                 }
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
@@ -875,17 +885,18 @@ __device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs,
         const int sub = wave / W, ws = wave % W;
         m = tl.g * MPT + sub * 64 + lane;
         owner = ws == 0;
-        kind = (TY && d.rho && m < M) ? (d.rho[m] != 0) : 0;
+        kind = (TY && d.rho && m < M) ? (gptr(d.rho)[m] != 0) : 0;
         if (m < M) {
-            const int32_t *col = d.C + m;
+            const gi32 *col = (const gi32 *)(d.C + m);
             for (int32_t k0 = ws; k0 < K; k0 += W * UNR) {
                 int32_t c[UNR], id[UNR];
+                bool ok[UNR];
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
                     const int32_t k = k0 + W * u;
-                    const bool ok = k < K && (!TY || !kind || s_rot[k]);
-                    id[u] = ok ? s_open[k] : 0;
-                    c[u] = ok ? col[(int64_t)id[u] * ldc] : INT32_MAX;
+                    ok[u] = k < K && (!TY || !kind || s_rot[k]);
+                    id[u] = ok[u] ? s_open[k] : 0;
+                    c[u] = ok[u] ? col[(int64_t)id[u] * ldc] : INT32_MAX;
                 }
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
@@ -931,9 +942,9 @@ __device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs,
     if (owner) {
         int32_t g1c = 0, g1d = 0;
         if (m < M) {
-            d.b1[m] = v1;
-            d.b2[m] = v2;
-            d.o1[m] = s1 | (kind << 16);
+            gptr(d.b1)[m] = v1;
+            gptr(d.b2)[m] = v2;
+            gptr(d.o1)[m] = s1 | (kind << 16);
             g1c = v1 <= R;
             g1d = g1c ? v1 : 0;
             const int32_t g2c = v2 <= R;
@@ -945,9 +956,9 @@ __device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs,
             }
         } else if (m < d.Mp) {
             // padding missions: a sentinel below every cost, so the sweep skips them
-            d.b1[m] = INT32_MIN;
-            d.b2[m] = INT32_MIN;
-            d.o1[m] = 0;
+            gptr(d.b1)[m] = INT32_MIN;
+            gptr(d.b2)[m] = INT32_MIN;
+            gptr(d.o1)[m] = 0;
         }
         const int32_t wc = wave_sum_x_i32(g1c);
         const int64_t wd = wave_sum_x_i64((int64_t)g1d);
@@ -961,8 +972,8 @@ __device__ __forceinline__ void refresh_tile(const InstDesc *__restrict__ descs,
     for (int k = threadIdx.x; k <= K; k += BS) {
         const u64 c = s_cov[k], dd = s_dist[k];
         if (c | dd) {
-            atomicAdd(&acc[k].cov, c);
-            atomicAdd(&acc[k].dist, dd);
+            gatomic_add(&acc[k].cov, c);
+            gatomic_add(&acc[k].dist, dd);
         }
     }
 }
@@ -1125,8 +1136,8 @@ __device__ void score_group(const InstDesc &d, const SolveState &st, int J, int 
             Gd + L.Ld[1 + k] + t1d[NC * r] + (two ? t1d[NC * r + 1] : 0) + (int64_t)L.bd[idx];
         const int32_t i = L.open[k], j = s_jrow[r];
         if (d.sc_cov) {
-            d.sc_cov[(int64_t)k * d.B + j] = cov;
-            d.sc_dist[(int64_t)k * d.B + j] = dist;
+            gptr(d.sc_cov)[(int64_t)k * d.B + j] = cov;
+            gptr(d.sc_dist)[(int64_t)k * d.B + j] = dist;
         }
         bool adm;
         uint64_t key = 0;
@@ -1166,13 +1177,12 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
                                            u64 *bd)
 {
     const int32_t K = d.K, R = d.R;
-    const v4i *b1v = reinterpret_cast<const v4i *>(d.b1);
-    const v4i *b2v = reinterpret_cast<const v4i *>(d.b2);
-    const v4i *o1v = reinterpret_cast<const v4i *>(d.o1);
-    const v4i *rows[J];
+    gv4i *b1v = (gv4i *)d.b1;
+    gv4i *b2v = (gv4i *)d.b2;
+    gv4i *o1v = (gv4i *)d.o1;
+    gv4i *rows[J];
 #pragma unroll
-    for (int r = 0; r < J; ++r)
-        rows[r] = reinterpret_cast<const v4i *>(d.C + (int64_t)jrow[r] * d.ldc);
+    for (int r = 0; r < J; ++r) rows[r] = (gv4i *)(d.C + (int64_t)jrow[r] * d.ldc);
     const int32_t qend = m1 >> 2;
     for (int32_t q0 = (m0 >> 2) + threadIdx.x; q0 < qend; q0 += U * BS) {
         v4i cv[U][J], vb1[U], vb2[U], vo1[U];
@@ -1194,6 +1204,8 @@ __device__ __forceinline__ void sweep_vec4(const InstDesc &d, const int32_t *jro
                 vo1[u] = (v4i)(0);
             }
         }
+        // every load of the step is issued before the first comparison waits
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -1256,7 +1268,6 @@ __device__ __forceinline__ void sweep_vec4_queued1(const InstDesc &d, const int3
     const int32_t K = d.K, R = d.R;
     const int32_t lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    typedef const __attribute__((address_space(1))) v4i gv4i;
     gv4i *b2v = (gv4i *)d.b2;
     gv4i *rows[J];
 #pragma unroll
@@ -1356,7 +1367,6 @@ __device__ __forceinline__ void sweep_vec4_queued4(const InstDesc &d, const int3
     const int32_t K = d.K, R = d.R;
     const int32_t lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    typedef const __attribute__((address_space(1))) v4i gv4i;
     gv4i *b1v = (gv4i *)d.b1;
     gv4i *b2v = (gv4i *)d.b2;
     gv4i *o1v = (gv4i *)d.o1;
@@ -1462,11 +1472,13 @@ __device__ __forceinline__ void sweep_scalar(const InstDesc &d, const int32_t *j
     const int32_t K = d.K, R = d.R;
     const int32_t mend = min(m1, d.M);
     const int64_t ldc = d.ldc;
+    const gi32 *C = (const gi32 *)d.C;
     for (int32_t m = m0 + threadIdx.x; m < mend; m += BS) {
         int32_t cv[J];
 #pragma unroll
-        for (int r = 0; r < J; ++r) cv[r] = d.C[(int64_t)jrow[r] * ldc + m];
-        const int32_t b1 = d.b1[m], b2 = d.b2[m], o1 = d.o1[m];
+        for (int r = 0; r < J; ++r) cv[r] = C[(int64_t)jrow[r] * ldc + m];
+        const int32_t b1 = ((const gi32 *)d.b1)[m], b2 = ((const gi32 *)d.b2)[m],
+                      o1 = ((const gi32 *)d.o1)[m];
         const int32_t g1c = b1 <= R, g1d = g1c ? b1 : 0;
         const int32_t g2c = b2 <= R, g2d = g2c ? b2 : 0;
 #pragma unroll
@@ -1537,6 +1549,12 @@ template <int BS, int J, int U, bool VEC4, bool NT, bool Q, int NC>
 __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs,
                                                   const Tile *__restrict__ tiles, int32_t step)
 {
+    // rows whose loads go out together: the in-place vector sweep takes
+    // groups of more than four rows in passes of four (the group's start-up
+    // and scoring are paid once for all its rows, with the registers of four)
+    constexpr int JL = (VEC4 && !Q && J > 4) ? 4 : J;
+    constexpr int P = J / JL;
+    static_assert(P * JL == J, "rows per pass");
     const Tile tl = sweep_tile(descs, tiles);
     const InstDesc &d = descs[tl.inst];
     if (!d.active) return;
@@ -1545,6 +1563,7 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     // The search state, this group's rows and the slot inputs go out in one
     // round of loads; the stop flag is checked once they are issued (before
     // anything is written to device memory).
+    // (a generic load: the state stays off the scalar path, measured faster)
     const SolveState st = *d.st;
     const bool scoring = d.nsplit == 1;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1559,18 +1578,76 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     __shared__ int64_t s_sum_d[NC * J];
     __shared__ Candidate s_red[BS / 64 + 1];
 
+    // The set-up loads (this group's rows by threads 0 .. J - 1, the first
+    // K + 1 slot inputs by threads 0 .. K) go out in one round, at clamped
+    // indices (every list holds at least one entry), and are waited for once;
+    // LDS takes them after the stop check.
     const int32_t nclosed = d.nclosed;
-    if (threadIdx.x < J) {
-        const int32_t js = tl.g * J + threadIdx.x;
+    const int32_t k0 = min((int32_t)threadIdx.x, K), k0o = min(k0, K - 1);
+    int32_t ld_jrow = 0, ld_jtabu = 0, ld_jhel = 0, ld_lc = 0, ld_open = 0, ld_otabu = 0,
+            ld_orot = 1;
+    int64_t ld_ld = 0;
+    if ((int32_t)threadIdx.x < J) {
+        const int32_t js = tl.g * J + (int32_t)threadIdx.x;
         const int32_t jc = js < nclosed ? js : 0;
-        s_jrow[threadIdx.x] = nclosed > 0 ? d.closed[jc] : 0;
-        if (scoring) {
-            s_jtabu[threadIdx.x] = nclosed > 0 ? d.closed_tabu[jc] : 0;
-            s_jhel[threadIdx.x] = NC == 2 && nclosed > 0 ? d.closed_hel[jc] : 0;
+        ld_jrow = gptr(d.closed)[jc];
+        ld_jtabu = gptr(d.closed_tabu)[jc];
+        if (NC == 2) ld_jhel = gptr(d.closed_hel)[jc];
+    }
+    if ((int32_t)threadIdx.x <= K) {
+        const __attribute__((address_space(1))) Acc *ga = gptr(d.acc[t & 1]);
+        u64 pc[kStripes], pd[kStripes];
+#pragma unroll
+        for (int q = 0; q < kStripes; ++q) {
+            pc[q] = ga[q * (K + 1) + k0].cov;
+            pd[q] = ga[q * (K + 1) + k0].dist;
+        }
+        ld_open = gptr(d.open)[k0o];
+        ld_otabu = gptr(d.open_tabu)[k0o];
+        if (NC == 2) ld_orot = gptr(d.open_rot)[k0o];
+        // (every load above is issued before the first sum waits)
+        __builtin_amdgcn_sched_barrier(0);
+        u64 sc = 0, sd = 0;
+#pragma unroll
+        for (int q = 0; q < kStripes; ++q) {
+            sc += pc[q];
+            sd += pd[q];
+        }
+        ld_lc = (int32_t)(int64_t)sc;
+        ld_ld = (int64_t)sd;
+    }
+    asm volatile("" ::"v"(ld_jrow), "v"(ld_jtabu), "v"(ld_jhel), "v"(ld_lc), "v"(ld_ld),
+                 "v"(ld_open), "v"(ld_otabu), "v"(ld_orot), "v"(st.stopped));
+    if (st.stopped) return;
+    if (threadIdx.x < J) {
+        s_jrow[threadIdx.x] = nclosed > 0 ? ld_jrow : 0;
+        s_jtabu[threadIdx.x] = nclosed > 0 ? ld_jtabu : 0;
+        s_jhel[threadIdx.x] = nclosed > 0 ? ld_jhel : 0;
+    }
+    if (scoring) {
+        if ((int32_t)threadIdx.x <= K) {
+            L.Lc[k0] = ld_lc;
+            L.Ld[k0] = ld_ld;
+            if ((int32_t)threadIdx.x < K) {
+                L.open[k0] = ld_open;
+                L.otabu[k0] = ld_otabu;
+                L.orot[k0] = ld_orot;
+            }
+        }
+        // (more than BS - 1 open slots: the rest one round at a time)
+        for (int32_t k = threadIdx.x + BS; k <= K; k += BS) {
+            int32_t c;
+            int64_t dd;
+            acc_sum(d.acc[t & 1], K, k, c, dd);
+            L.Lc[k] = c;
+            L.Ld[k] = dd;
+            if (k < K) {
+                L.open[k] = d.open[k];
+                L.otabu[k] = d.open_tabu[k];
+                L.orot[k] = NC == 2 ? d.open_rot[k] : 1;
+            }
         }
     }
-    if (scoring) load_slot_inputs(d, t, L, NC == 2);
-    if (st.stopped) return;
     if (tl.g == 0 && tl.sp == 0) sweep_housekeeping(d, t);
     for (int q = threadIdx.x; q < J * K; q += BS) {
         L.bd[q] = 0;
@@ -1578,27 +1655,70 @@ __global__ __launch_bounds__(BS) void k_sweep(const InstDesc *__restrict__ descs
     }
     __syncthreads();
 
-    int32_t jrow[J];
+    const int32_t m0 = tl.sp * d.chunk;
+    const int32_t m1 = min(d.Mp, m0 + d.chunk);
+    if constexpr (P == 1) {
+        int32_t jrow[J];
 #pragma unroll
-    for (int r = 0; r < J; ++r) jrow[r] = s_jrow[r];
-    int32_t t1c[NC * J];
-    int64_t t1d[NC * J];
+        for (int r = 0; r < J; ++r) jrow[r] = s_jrow[r];
+        int32_t t1c[NC * J];
+        int64_t t1d[NC * J];
 #pragma unroll
-    for (int r = 0; r < NC * J; ++r) {
-        t1c[r] = 0;
-        t1d[r] = 0;
+        for (int r = 0; r < NC * J; ++r) {
+            t1c[r] = 0;
+            t1d[r] = 0;
+        }
+        if (nclosed > 0) {
+            if (VEC4 && Q)
+                sweep_vec4_queued<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+            else if (VEC4)
+                sweep_vec4<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+            else
+                sweep_scalar<BS, J, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
+        }
+        reduce_rows<BS, NC * J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
+    } else {
+        // P passes over the chunk, JL rows each: every wave sums its common
+        // terms of a pass into LDS; the workgroup adds the waves once at the end
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll 1
+        for (int p = 0; p < P; ++p) {
+            int32_t jrow[JL];
+#pragma unroll
+            for (int r = 0; r < JL; ++r) jrow[r] = s_jrow[p * JL + r];
+            int32_t t1c[NC * JL];
+            int64_t t1d[NC * JL];
+#pragma unroll
+            for (int r = 0; r < NC * JL; ++r) {
+                t1c[r] = 0;
+                t1d[r] = 0;
+            }
+            if (nclosed > 0)
+                sweep_vec4<BS, JL, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc + p * JL * K,
+                                              L.bd + p * JL * K);
+#pragma unroll
+            for (int r = 0; r < NC * JL; ++r) {
+                const int32_t c = wave_sum_i32(t1c[r]);
+                const int64_t dd = wave_sum_i64(t1d[r]);
+                if (lane == 0) {
+                    s_t1c[wave][NC * JL * p + r] = c;
+                    s_t1d[wave][NC * JL * p + r] = dd;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < NC * J) {
+            int32_t c = 0;
+            int64_t dd = 0;
+            for (int w = 0; w < BS / 64; ++w) {
+                c += s_t1c[w][threadIdx.x];
+                dd += s_t1d[w][threadIdx.x];
+            }
+            s_sum_c[threadIdx.x] = c;
+            s_sum_d[threadIdx.x] = dd;
+        }
+        __syncthreads();
     }
-    if (nclosed > 0) {
-        const int32_t m0 = tl.sp * d.chunk;
-        const int32_t m1 = min(d.Mp, m0 + d.chunk);
-        if (VEC4 && Q)
-            sweep_vec4_queued<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
-        else if (VEC4)
-            sweep_vec4<BS, J, U, NT, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
-        else
-            sweep_scalar<BS, J, NC>(d, jrow, m0, m1, t1c, t1d, L.bc, L.bd);
-    }
-    reduce_rows<BS, NC * J>(t1c, t1d, s_t1c, s_t1d, s_sum_c, s_sum_d);
 
     if (scoring) {
         score_group<BS>(d, st, J, NC, t, tl.g, s_jrow, s_jtabu, s_jhel, L, s_sum_c, s_sum_d,
@@ -1849,28 +1969,119 @@ __device__ __forceinline__ void visit_sparse(int32_t c, int32_t b1, int32_t b2, 
     }
 }
 
-// The closed bases of block q as rows (ascending id): s_jrow / s_jslot /
-// s_jtabu, and s_rowof[local id] = row or -1.  Called by the first wave.
-__device__ __forceinline__ void sparse_rows(const InstDesc &d, int32_t q, bool with_tabu,
-                                            int32_t *s_jrow, int32_t *s_jslot, int32_t *s_jtabu,
-                                            int32_t *s_jhel, int32_t *s_rowof, int32_t *s_nrows)
+// Set-up loads of a block kernel of the sparse sweep, issued together and
+// waited for once: the search state, the list slot and tabu expiry of the
+// block's 64 base ids (first wave, one per lane), and the slot inputs of
+// slot k = thread for threads 0 .. K (G and L_k summed over the stripes, open
+// base, its tabu expiry).  Indices are clamped, so every load is in bounds.
+struct SparseSetup {
+    SolveState st;
+    int32_t slot, tabu;   // base q * 64 + lane: slot (>= 0 closed, < 0 open) ...
+    bool inb;             // ... if the base exists (below B)
+    int32_t lc, open, otabu;
+    int64_t ld;
+};
+
+__device__ __forceinline__ SparseSetup sparse_setup(const InstDesc &d, int32_t t, int32_t q)
+{
+    SparseSetup u;
+    // (a generic load: the state stays off the scalar path, measured faster)
+    u.st = *d.st;
+    const int32_t K = d.K;
+    u.slot = -1;
+    u.tabu = 0;
+    u.inb = false;
+    u.lc = 0;
+    u.ld = 0;
+    u.open = 0;
+    u.otabu = 0;
+    // (only the first wave uses the block's slots, and threads 0 .. K the
+    // slot inputs: the other waves skip both)
+    if (threadIdx.x < kSparseW) {
+        const int32_t b = q * kSparseW + (int32_t)threadIdx.x;
+        const int32_t bb = min(b, d.B - 1);
+        u.slot = gptr(d.base_slot)[bb];
+        u.tabu = gptr(d.base_tabu)[bb];
+        u.inb = b < d.B;
+    }
+    if ((int32_t)threadIdx.x <= K) {
+        const int32_t k0 = threadIdx.x, k0o = min(k0, K - 1);
+        const __attribute__((address_space(1))) Acc *ga = gptr(d.acc[t & 1]);
+        u64 pc[kStripes], pd[kStripes];
+#pragma unroll
+        for (int s = 0; s < kStripes; ++s) {
+            pc[s] = ga[s * (K + 1) + k0].cov;
+            pd[s] = ga[s * (K + 1) + k0].dist;
+        }
+        u.open = gptr(d.open)[k0o];
+        u.otabu = gptr(d.open_tabu)[k0o];
+        // (every load above is issued before the first sum waits)
+        __builtin_amdgcn_sched_barrier(0);
+        u64 sc = 0, sd = 0;
+#pragma unroll
+        for (int s = 0; s < kStripes; ++s) {
+            sc += pc[s];
+            sd += pd[s];
+        }
+        u.lc = (int32_t)(int64_t)sc;
+        u.ld = (int64_t)sd;
+    }
+    asm volatile("" ::"v"(u.st.stopped), "v"(u.st.pass), "v"(u.st.cur_cov), "v"(u.st.best_cov),
+                 "v"(u.st.cur_dist), "v"(u.st.best_dist), "v"(u.st.have_last),
+                 "v"(u.st.last_key), "v"(u.slot), "v"(u.tabu), "v"(u.lc), "v"(u.ld),
+                 "v"(u.open), "v"(u.otabu));
+    return u;
+}
+
+// The closed bases of the block as rows (ascending id): s_jrow / s_jslot /
+// s_jtabu, and s_rowof[local id] = row or -1.  Called by the first wave with
+// its set-up loads.
+__device__ __forceinline__ void sparse_rows(const SparseSetup &u, int32_t q, int32_t *s_jrow,
+                                            int32_t *s_jslot, int32_t *s_jtabu, int32_t *s_jhel,
+                                            int32_t *s_rowof, int32_t *s_nrows)
 {
     const int lane = threadIdx.x & 63;
     const int32_t b = q * kSparseW + lane;
-    // (slot and expiry by base id: one round of loads)
-    const int32_t slot = b < d.B ? d.base_slot[b] : -1;
-    const int32_t tabu = b < d.B && with_tabu ? d.base_tabu[b] : 0;
-    const bool closed = slot >= 0;
+    const bool closed = u.inb && u.slot >= 0;
     const u64 mask = __builtin_amdgcn_ballot_w64(closed);
     const int32_t row = (int32_t)__builtin_popcountll(mask & ((1ull << lane) - 1));
     s_rowof[lane] = closed ? row : -1;
     if (closed) {
         s_jrow[row] = b;
-        s_jslot[row] = slot;
-        s_jtabu[row] = tabu;
+        s_jslot[row] = u.slot;
+        s_jtabu[row] = u.tabu;
         s_jhel[row] = 0;
     }
     if (lane == 0) *s_nrows = (int32_t)__builtin_popcountll(mask);
+}
+
+// The slot inputs to LDS: slot k = thread from the set-up loads, any further
+// slots (K >= the workgroup size) loaded here.
+__device__ __forceinline__ void sparse_slot_inputs(const InstDesc &d, int32_t t,
+                                                   const SparseSetup &u, const SweepLds &L)
+{
+    const int32_t K = d.K;
+    if ((int32_t)threadIdx.x <= K) {
+        L.Lc[threadIdx.x] = u.lc;
+        L.Ld[threadIdx.x] = u.ld;
+        if ((int32_t)threadIdx.x < K) {
+            L.open[threadIdx.x] = u.open;
+            L.otabu[threadIdx.x] = u.otabu;
+            L.orot[threadIdx.x] = 1;
+        }
+    }
+    for (int32_t k = threadIdx.x + blockDim.x; k <= K; k += blockDim.x) {
+        int32_t c;
+        int64_t dd;
+        acc_sum(d.acc[t & 1], K, k, c, dd);
+        L.Lc[k] = c;
+        L.Ld[k] = dd;
+        if (k < K) {
+            L.open[k] = d.open[k];
+            L.otabu[k] = d.open_tabu[k];
+            L.orot[k] = 1;
+        }
+    }
 }
 
 // One element of a walk: the dense visit's terms while c < b2 and the base is
@@ -1929,8 +2140,8 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
     if (!d.active) return;
     const int32_t t = step - d.start_step;
     if (t < 1 || t > d.N) return;
-    // (the search state, the block's rows and the slot inputs go out in one
-    // round of loads; the stop flag is checked once they are issued)
+    // (the state, the block's rows and the slot inputs are loaded where they
+    // are used: measured faster here than one round waited for by every wave)
     const SolveState st = *d.st;
     const bool scoring = d.nsplit == 1;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1947,7 +2158,12 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
     if (threadIdx.x < kSparseW) {
         s_t1c[threadIdx.x] = 0;
         s_t1d[threadIdx.x] = 0;
-        sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
+        SparseSetup su;
+        const int32_t b = tl.g * kSparseW + (int32_t)threadIdx.x;
+        su.inb = b < d.B;
+        su.slot = su.inb ? gptr(d.base_slot)[b] : -1;
+        su.tabu = su.inb ? gptr(d.base_tabu)[b] : 0;
+        sparse_rows(su, tl.g, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
     }
     if (scoring) load_slot_inputs(d, t, L, false);
     if (st.stopped) return;
@@ -1962,7 +2178,6 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t m0 = tl.sp * d.chunk, m1 = min(d.Mp, m0 + d.chunk);
     const int64_t Mp = d.Mp;
-    typedef const __attribute__((address_space(1))) v4i gv4i;
     typedef const __attribute__((address_space(1))) uint32_t gu32;
     typedef const __attribute__((address_space(1))) uint64_t gu64;
     const int32_t *hc = d.lst_cost + (int64_t)tl.g * kSparseHead * Mp;
@@ -2086,8 +2301,8 @@ __global__ __launch_bounds__(BS, 8) void k_sweep_sparse(const InstDesc *__restri
             const int32_t r = idx / K1, k = idx - r * K1;
             const int32_t c = k == 0 ? s_t1c[r] : L.bc[r * K + k - 1];
             const u64 dd = k == 0 ? s_t1d[r] : L.bd[r * K + k - 1];
-            if (c) atomicAdd(pc + idx, (unsigned int)c);
-            if (dd) atomicAdd(pd + idx, dd);
+            if (c) gatomic_add(pc + idx, (unsigned int)c);
+            if (dd) gatomic_add(pd + idx, dd);
         }
     }
 }
@@ -2123,8 +2338,6 @@ __device__ __forceinline__ void score_part(const InstDesc *__restrict__ descs, c
     if (!d.active) return;
     const int32_t t = step - d.start_step;
     if (t < 1 || t > d.N) return;
-    const SolveState st = *d.st;
-    if (st.stopped) return;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RP = kSparseW / kScoreParts;   // rows per part
     const int32_t K = d.K, K1 = K + 1, part = tl.sp, r0 = part * RP;
@@ -2144,12 +2357,18 @@ __device__ __forceinline__ void score_part(const InstDesc *__restrict__ descs, c
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int32_t idx = threadIdx.x + i * BS;
-        pcv[i] = idx < RP * K1 ? d.part_cov[base + idx] : 0;
-        pdv[i] = idx < RP * K1 ? d.part_dist[base + idx] : 0;
+        const int32_t at = idx < RP * K1 ? idx : 0;   // (in bounds: loaded, then dropped)
+        pcv[i] = gptr(d.part_cov)[base + at];
+        pdv[i] = gptr(d.part_dist)[base + at];
     }
+    const SparseSetup su = sparse_setup(d, t, tl.g);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) asm volatile("" ::"v"(pcv[i]), "v"(pdv[i]));
+    const SolveState &st = su.st;
+    if (st.stopped) return;
     if (threadIdx.x < kSparseW)
-        sparse_rows(d, tl.g, true, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
-    load_slot_inputs(d, t, L, false);
+        sparse_rows(su, tl.g, s_jrow, s_jslot, s_jtabu, s_jhel, s_rowof, &s_nrows);
+    sparse_slot_inputs(d, t, su, L);
     __syncthreads();
     const int32_t nr = min(max(s_nrows - r0, 0), RP);
 #pragma unroll
@@ -2158,8 +2377,8 @@ __device__ __forceinline__ void score_part(const InstDesc *__restrict__ descs, c
         if (idx >= RP * K1) continue;
         const int32_t c = pcv[i];
         const int64_t dd = pdv[i];
-        d.part_cov[base + idx] = 0;
-        d.part_dist[base + idx] = 0;
+        gptr(d.part_cov)[base + idx] = 0;
+        gptr(d.part_dist)[base + idx] = 0;
         if (idx >= nr * K1) continue;
         const int32_t r = idx / K1, k = idx - r * K1;
         if (k == 0) {
@@ -2842,7 +3061,7 @@ int choose_rows_per_group(int32_t nclosed, int32_t M, int64_t total_rows, int32_
     else if (nclosed >= 1024)
         J = 2;
     J = env_int("FS_SWEEP_J", J);
-    if (J != 1 && J != 2 && J != 4 && J != 8) J = 1;
+    if (J != 1 && J != 2 && J != 4 && J != 8 && J != 16) J = 1;
     while (J > 1 && sweep_lds_bytes(J, K) > 56 * 1024) J >>= 1;
     return J;
 }
@@ -3089,6 +3308,12 @@ fs_status sweep_rows(const EngineTables &t, const EngineConfig &c, int32_t step,
     case 8:
         return c.typed ? launch_sweep_typed<8>(t, c, step, s, timed)
                        : launch_sweep_ju<8, 1>(t, c, step, s, timed);
+    case 16:
+        // (untyped, in place, one load in flight: the launch set's rule)
+        if (c.typed || !c.vec4 || c.queue)
+            return fail(FS_E_INTERNAL, "16-row sweep groups need the in-place vector sweep");
+        return c.nt ? launch_sweep_t<16, 1, true, true, false, 1>(t, c, step, s, timed)
+                    : launch_sweep_t<16, 1, true, false, false, 1>(t, c, step, s, timed);
     default: return fail(FS_E_INTERNAL, "unsupported sweep row count %d", c.J);
     }
 }

@@ -57,6 +57,13 @@ fs_status build_launch_set(const std::vector<InstSpec> &specs, int target_wg, La
     cfg.typed = false;
     for (const InstSpec &p : specs) cfg.typed = cfg.typed || p.typed;
     if (cfg.typed) cfg.U = 1;   // typed sweeps keep one load in flight
+    // 16-row groups: untyped in-place vector sweeps with one load in flight
+    // (four rows per pass)
+    if (cfg.J == 16 && (cfg.typed || !vec4)) cfg.J = 8;
+    if (cfg.J == 16) {
+        cfg.queue = false;
+        cfg.U = 1;
+    }
     ls.Bmax = Bmax;
     // the sparse sweep: one homogeneous instance with closed bases and
     // K <= kSparseMaxK (its bins for a block of bases sit in LDS); by default
@@ -329,6 +336,8 @@ fs_status tune_sweep(LaunchSet &ls, hipStream_t s)
             for (int w = 0; w < 2; ++w) {
                 if (w && ls.cfg.J > 2 && (q || U != 1)) continue;   // no such wide form
                 if (ls.cfg.typed && U != 1) continue;                // typed: U = 1 only
+                if (ls.cfg.J >= 8 && U != 1) continue;               // U = 1 only
+                if (ls.cfg.J == 16 && q) continue;                   // in place only
                 EngineConfig c = ls.cfg;
                 c.U = U;
                 c.queue = q != 0;

@@ -88,6 +88,7 @@ def test_fleet_move_scores_random_placements():
 #  1024-thread sweep workgroups, one mission per refresh thread); typed
 #  sweeps keep one load in flight
 GEOMETRIES = [(1, 1, 1, 1, 0, 0), (2, 3, 0, 0, 0, 1), (4, 1, 1, 1, 0, 0), (8, 5, 1, 1, 0, 1),
+              (16, 2, 1, 0, 0, 0),
               (1, 7, 0, 1, 1, 1), (4, 2, 1, 0, 0, 0), (1, 1, 1, 0, 1, 0), (2, 1, 0, 1, 1, 1),
               (4, 1, 1, 0, 1, 0), (8, 1, 0, 0, 1, 1)]
 

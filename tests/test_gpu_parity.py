@@ -172,7 +172,8 @@ def test_move_scores_small_and_medium():
 GEOMETRIES = [(1, 1, 1, 1, 1, 0, 0), (2, 3, 2, 0, 0, 0, 1), (4, 1, 4, 1, 1, 0, 0),
               (8, 5, 1, 1, 1, 0, 1), (1, 7, 4, 0, 1, 1, 0), (2, 1, 4, 1, 1, 1, 1),
               (4, 2, 2, 1, 0, 0, 0), (1, 1, 2, 1, 0, 1, 1), (2, 2, 1, 1, 0, 1, 0),
-              (4, 1, 1, 1, 0, 1, 1), (8, 1, 1, 0, 0, 1, 0)]
+              (4, 1, 1, 1, 0, 1, 1), (8, 1, 1, 0, 0, 1, 0), (16, 1, 1, 1, 0, 0, 0),
+              (16, 3, 1, 0, 0, 1, 1), (8, 2, 1, 1, 0, 0, 1)]
 
 
 @pytest.mark.parametrize("J,split,U,nt,q,w,rw", GEOMETRIES)

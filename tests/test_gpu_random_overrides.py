@@ -44,7 +44,7 @@ def _lib():
 def draw_env(rng):
     env = {}
     if rng.random() < 0.5:
-        env["FS_SWEEP_J"] = int(rng.choice([1, 2, 4, 8]))
+        env["FS_SWEEP_J"] = int(rng.choice([1, 2, 4, 8, 16]))
     if rng.random() < 0.5:
         env["FS_SWEEP_U"] = int(rng.choice([1, 2, 4]))
     if rng.random() < 0.5:
