@@ -149,6 +149,20 @@ __global__ __launch_bounds__(kBlock) void k_mission_legs(const double *__restric
     packed[m] = (uint32_t)p | ((uint32_t)d << 16);
 }
 
+// Per hospital: latitude and longitude in radians and the cosine of the
+// latitude (the same expressions as in the legs above, so the same doubles).
+__global__ __launch_bounds__(kBlock) void k_hosp_prep(const double *__restrict__ hosp, int32_t H,
+                                                      double *__restrict__ hp)
+{
+    const int32_t h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= H) return;
+    const double phi = hosp[2 * (int64_t)h] * kDeg2Rad;
+    const double psi = hosp[2 * (int64_t)h + 1] * kDeg2Rad;
+    hp[h] = phi;
+    hp[H + h] = psi;
+    hp[2 * (int64_t)H + h] = cos(phi);
+}
+
 // One workgroup per base: the leg between the base and every hospital in LDS,
 // then C[b][m] = (leg(b, p) + pd) + leg(d, b) for every mission, in the
 // direct form's order.  The haversine above is symmetric bit for bit (the
@@ -156,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_mission_legs(const double *__restric
 // the cosines commutes), so one leg per hospital serves both directions and
 // the table is bitwise the direct form's (tested).
 __global__ __launch_bounds__(kIndexedBlock) void k_cost_indexed(
-    const double *__restrict__ bases, const double *__restrict__ hosp, int32_t H,
+    const double *__restrict__ bases, const double *__restrict__ hp, int32_t H,
     const double *__restrict__ pd, const uint32_t *__restrict__ packed, int32_t M, double two_r,
     int32_t legs, int32_t *__restrict__ C, double *__restrict__ Cf, int64_t ldc)
 {
@@ -166,12 +180,9 @@ __global__ __launch_bounds__(kIndexedBlock) void k_cost_indexed(
     const double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
     const double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
     const double cos_b = cos(phi_b);
-    for (int32_t h = threadIdx.x; h < H; h += kIndexedBlock) {
-        const double phi_h = hosp[2 * (int64_t)h] * kDeg2Rad;
-        const double psi_h = hosp[2 * (int64_t)h + 1] * kDeg2Rad;
-        const double cos_h = cos(phi_h);
-        leg[h] = haversine(phi_b, psi_b, cos_b, phi_h, psi_h, cos_h, two_r);
-    }
+    // (hospital angles and cosines from k_hosp_prep)
+    for (int32_t h = threadIdx.x; h < H; h += kIndexedBlock)
+        leg[h] = haversine(phi_b, psi_b, cos_b, hp[h], hp[H + h], hp[2 * (int64_t)H + h], two_r);
     __syncthreads();
     const int64_t row = (int64_t)b * ldc;
     // four missions per thread and step, their loads issued together
@@ -276,15 +287,21 @@ extern "C" fs_status fs_build_cost_table_indexed(const double *base_latlon_deg, 
     const double two_r = 2.0 * r;
     char *buf = nullptr;
     const size_t pd_bytes = sizeof(double) * (size_t)M, pk_bytes = sizeof(uint32_t) * (size_t)M;
-    FS_HIP(hipMallocAsync((void **)&buf, pd_bytes + pk_bytes + 256, s));
-    double *pd = (double *)buf;
-    uint32_t *packed = (uint32_t *)(buf + pd_bytes);
-    int32_t *bad = (int32_t *)(buf + pd_bytes + pk_bytes);   // (12 M bytes: 4-aligned)
+    const size_t hp_bytes = sizeof(double) * 3 * (size_t)H;
+    FS_HIP(hipMallocAsync((void **)&buf, hp_bytes + pd_bytes + pk_bytes + 256, s));
+    double *hp = (double *)buf;
+    double *pd = (double *)(buf + hp_bytes);
+    uint32_t *packed = (uint32_t *)(buf + hp_bytes + pd_bytes);
+    int32_t *bad = (int32_t *)(buf + hp_bytes + pd_bytes + pk_bytes);   // (4-aligned)
     int32_t nbad = 0;
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
     if (e == hipSuccess) {
         k_mission_legs<<<(M + kBlock - 1) / kBlock, kBlock, 0, s>>>(hosp_latlon_deg, H, mission_ph,
                                                                    M, two_r, pd, packed, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_hosp_prep<<<(H + kBlock - 1) / kBlock, kBlock, 0, s>>>(hosp_latlon_deg, H, hp);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
@@ -294,8 +311,8 @@ extern "C" fs_status fs_build_cost_table_indexed(const double *base_latlon_deg, 
         e = hipFuncSetAttribute((const void *)k_cost_indexed,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess) {
-            k_cost_indexed<<<B, kIndexedBlock, lds, s>>>(base_latlon_deg, hosp_latlon_deg, H, pd,
-                                                         packed, M, two_r, legs, C, Cf, ldc);
+            k_cost_indexed<<<B, kIndexedBlock, lds, s>>>(base_latlon_deg, hp, H, pd, packed, M,
+                                                         two_r, legs, C, Cf, ldc);
             e = hipGetLastError();
         }
     }
