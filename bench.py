@@ -251,6 +251,9 @@ def main():
                     help="skip the seed-portfolio leg (permuted local and Tabu searches)")
     ap.add_argument("--no-fleet", action="store_true",
                     help="skip the heterogeneous-fleet leg (typed relocation search)")
+    ap.add_argument("--batch-no-plain", action="store_true",
+                    help="ragged-batch leg: the batched launch only (one timed run, no "
+                         "per-instance solves; for profiling)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the ragged-batch leg (one launch vs one solve per instance)")
     args = ap.parse_args()
@@ -317,7 +320,8 @@ def main():
     batch = None
     if not args.no_batch:
         from paper_2001_05291_amd import batchbench
-        batch = batchbench.run(fs, torch, log=log)
+        batch = batchbench.run(fs, torch, log=log, plain=not args.batch_no_plain,
+                               reps=1 if args.batch_no_plain else 2)
 
     serve = None
     if not args.no_serve:
