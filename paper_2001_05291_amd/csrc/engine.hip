@@ -1768,9 +1768,11 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     const int32_t nmg = (d.Mp + 63) / 64;
     const int32_t q = (int32_t)blockIdx.x / nmg, mg = (int32_t)blockIdx.x - q * nmg;
     // (row pitches of 65 words and 68 bytes: a wave writing one column
-    // touches a different bank in every lane)
+    // touches a different bank in every lane; the sorted costs reuse the
+    // tile's LDS once every wave holds its columns in registers, which keeps
+    // the workgroup at 21 KB of LDS)
     __shared__ int32_t s_c[kSparseW][65];
-    __shared__ int32_t s_cost[kSparseW][65];
+    int32_t (*s_cost)[65] = s_c;
     __shared__ __align__(16) unsigned char s_id[kSparseW][68];
     // every load of the tile in flight before the first LDS write (each
     // thread: one mission, every fourth base of the block)
@@ -1800,12 +1802,17 @@ __global__ __launch_bounds__(kBlock) void k_sparse_build(const InstDesc *__restr
     // the sentinel as 2^26 - 1, in the same order; a haversine round trip is
     // below 6.1e7 m < 2^26 - 1, so real tables take this path)
     constexpr int PER_WAVE = 64 / (kBlock / 64), IL = 4;
+    int32_t col_c[PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) col_c[i] = s_c[lane][wave * PER_WAVE + i];
+    __syncthreads();   // (the tile is read; its LDS now takes the sorted costs)
+#pragma unroll
     for (int i0 = 0; i0 < PER_WAVE; i0 += IL) {
         int32_t cst[IL];
         bool fits = true;
 #pragma unroll
         for (int q = 0; q < IL; ++q) {
-            cst[q] = s_c[lane][wave * PER_WAVE + i0 + q];
+            cst[q] = col_c[i0 + q];
             fits = fits && (cst[q] == INT32_MAX || (uint32_t)cst[q] < kNarrowTop);
         }
         if (__builtin_amdgcn_ballot_w64(!fits) == 0) {
