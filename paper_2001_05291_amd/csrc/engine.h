@@ -119,6 +119,7 @@ struct EngineConfig {
     int J_tall = 4;     // rows per workgroup of the sweep_tall tiles
     int U_tall = 1;
     int Kmax_tall = 1;  // largest K among the sweep_tall instances
+    int Kmax_long = 1;  // largest K among the sweep_long instances
     // missions per refresh workgroup: kRefreshMissions (the waves split the
     // open slots of 64 missions) or kBlock (one mission per thread, all slots;
     // for small K and many missions); the refresh tiles are built to match
@@ -153,6 +154,9 @@ struct EngineTables {
     // workgroup (tall instances among short ones; never split)
     const Tile *sweep_tall = nullptr;
     int nsweep_tall = 0;
+    // the same for instances with long rows, swept by 1024-thread workgroups
+    const Tile *sweep_long = nullptr;
+    int nsweep_long = 0;
     const Tile *score = nullptr;   // row groups of instances with nsplit > 1
     int nscore = 0;
     const Tile *refresh = nullptr;

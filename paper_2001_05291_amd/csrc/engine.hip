@@ -3403,6 +3403,20 @@ fs_status engine_sweep(const EngineTables &t, const EngineConfig &c, int32_t ste
         ct.wide = false;
         FS_TRY(sweep_rows(tall, ct, step, s));
     }
+    if (t.nsweep_long > 0) {   // (1024-thread workgroups where the form has them)
+        EngineTables lng = t;
+        lng.sweep = t.sweep_long;
+        lng.nsweep = t.nsweep_long;
+        lng.score = nullptr;
+        lng.nscore = 0;
+        lng.single = false;
+        EngineConfig cl = c;
+        cl.J = c.J_tall;
+        cl.U = c.U_tall;
+        cl.Kmax = c.Kmax_long;
+        cl.wide = true;
+        FS_TRY(sweep_rows(lng, cl, step, s));
+    }
     return FS_OK;
 }
 

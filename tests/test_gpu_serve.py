@@ -88,7 +88,8 @@ def test_two_sweep_classes_in_one_round(fs, monkeypatch):
     """Instances with at least 16 closed bases and short rows are swept four
     rows per workgroup, the others one row per workgroup, as two tile classes
     in the same rounds; then again with the many-rows threshold lowered so the
-    rule's other branch is taken too, each with in-place and queued scoring."""
+    rule's other branch is taken too, each with in-place and queued scoring,
+    and with long-row instances as a third class."""
     insts, reqs = make_workload(8, 32, seed=7, sizes=((8, 60), (100, 1500), (2, 12)))
     ncl = [w["inst"].B - w["K"] for w in insts]
     assert any(n >= 16 for n in ncl) and any(n < 16 for n in ncl)
@@ -103,6 +104,14 @@ def test_two_sweep_classes_in_one_round(fs, monkeypatch):
     served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
     assert_same(served, plain)
     monkeypatch.delenv("FS_SERVE_TALL_ROWS")
+    served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
+    assert_same(served, plain)
+    # four-row instances with rows of at least 1,000 missions as a third
+    # class (1024-thread workgroups), in place and queued
+    monkeypatch.setenv("FS_SERVE_LONG_ROWS", "1000")
+    served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
+    assert_same(served, plain)
+    monkeypatch.setenv("FS_SERVE_QUEUE", "0")
     served, _ = serve_all(fs, insts, reqs, T=5, N=30, max_slots=4)
     assert_same(served, plain)
 
