@@ -1,0 +1,94 @@
+"""The oracle's C code under AddressSanitizer and UndefinedBehaviorSanitizer.
+
+`tests/oracle_driver.c` calls every exported oracle function on small seeded
+instances (padded row pitch, K = 1 and K = B, R = 0, T = 0, N = 0, one mission,
+both leg counts, all search modes, the typed fleet, the exhaustive optima) and
+prints a digest of each call's outputs.  It is built twice with gcc: plainly,
+and with ASan + UBSan (any report aborts the run).  Every run must exit with
+status 0 and print the same digests, whatever the OpenMP thread count and
+whatever value fills the table's row padding (which no function may read).
+
+A control program with one out-of-bounds read shows that the sanitizer build
+does catch such a read on this machine.
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE_SRCS = [os.path.join(ROOT, "oracle", n)
+               for n in ("fleetstage_oracle.c", "fleet_oracle.c", "perm_oracle.c")]
+DRIVER = os.path.join(ROOT, "tests", "oracle_driver.c")
+COMMON = ["-std=c11", "-fopenmp", "-fno-fast-math", "-ffp-contract=off", "-Wall", "-Wextra"]
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=all"]
+
+pytestmark = pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not found")
+
+
+def _gcc(out, srcs, flags):
+    cmd = ["gcc", *COMMON, *flags, "-o", str(out), *srcs, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+
+
+def _run(exe, *args):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    return subprocess.run([str(exe), *map(str, args)], capture_output=True, text=True,
+                          timeout=300, env=env)
+
+
+@pytest.fixture(scope="module")
+def builds(tmp_path_factory):
+    d = tmp_path_factory.mktemp("sanitized_oracle")
+    plain, san = d / "plain", d / "sanitized"
+    _gcc(plain, [DRIVER, *ORACLE_SRCS], ["-O2"])
+    _gcc(san, [DRIVER, *ORACLE_SRCS], SANITIZE)
+    return d, plain, san
+
+
+def test_sanitizer_catches_an_out_of_bounds_read(builds):
+    d, _, _ = builds
+    src = d / "control.c"
+    src.write_text("#include <stdlib.h>\n"
+                   "int main(int argc, char **argv) {\n"
+                   "    (void)argv;\n"
+                   "    int *a = malloc(4 * sizeof(int));\n"
+                   "    for (int i = 0; i < 4; ++i) a[i] = i;\n"
+                   "    int v = a[3 + argc];   /* one past the end */\n"
+                   "    free(a);\n"
+                   "    return v == 12345;\n"
+                   "}\n")
+    exe = d / "control"
+    _gcc(exe, [str(src)], SANITIZE)
+    r = _run(exe)
+    assert r.returncode != 0
+    # UBSan's object-size check or ASan's shadow check, whichever sees it first
+    assert "heap-buffer-overflow" in r.stderr or "insufficient space" in r.stderr, r.stderr
+
+
+def test_oracle_clean_under_sanitizers(builds):
+    _, plain, san = builds
+    ref = _run(plain, 2, -7)
+    assert ref.returncode == 0, ref.stderr
+    lines = ref.stdout.splitlines()
+    assert len(lines) > 60
+    # every function and search mode appears
+    for name in ("scalars", "cost_table(3 legs)", "cost_table(2 legs)", "row_sums",
+                 "rank_bases", "value+assign", "move_scores", "tabu", "local_search",
+                 "perm_local", "perm_tabu", "fleet rank+scores", "fleet_tabu",
+                 "fleet_local_search", "brute_optimum", "fleet_brute_optimum"):
+        assert any(l.startswith(name + " ") for l in lines), name
+    for exe, threads, pad in ((san, 2, -7), (san, 4, 2**31 - 1), (plain, 1, 0),
+                              (plain, 8, -(2**31))):
+        r = _run(exe, threads, pad)
+        assert r.returncode == 0, (exe.name, threads, pad, r.stderr[-4000:])
+        assert "runtime error" not in r.stderr, r.stderr[-4000:]
+        assert "Sanitizer" not in r.stderr, r.stderr[-4000:]
+        assert r.stdout == ref.stdout, (exe.name, threads, pad)
