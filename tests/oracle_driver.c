@@ -346,8 +346,12 @@ int main(int argc, char **argv)
         h_bytes(&v, sizeof v);
     }
     for (int i = 0; i < 64; ++i) {
-        const double d = fso_haversine(uniform(-89, 89), uniform(-179, 179), uniform(-89, 89),
-                                       uniform(-179, 179), EARTH_R);
+        /* one draw per statement: the order of a call's arguments is unspecified */
+        const double lat_a = uniform(-89, 89);
+        const double lon_a = uniform(-179, 179);
+        const double lat_b = uniform(-89, 89);
+        const double lon_b = uniform(-179, 179);
+        const double d = fso_haversine(lat_a, lon_a, lat_b, lon_b, EARTH_R);
         h_bytes(&d, sizeof d);
         const uint64_t z = fso_mix64((uint64_t)i * 0x9E3779B97F4A7C15ull);
         const uint64_t p = fso_perm_priority(0x1234u + (uint64_t)i, i % 5, 37, i % 7, i % 37);

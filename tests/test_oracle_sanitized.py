@@ -10,6 +10,12 @@ whatever value fills the table's row padding (which no function may read).
 
 A control program with one out-of-bounds read shows that the sanitizer build
 does catch such a read on this machine.
+
+ThreadSanitizer: the same driver built by LLVM's clang against LLVM's OpenMP
+runtime, with the Archer tool supplying OpenMP's synchronisation to the race
+detector (without it every fork and join of a parallel region reads as a
+race), at 2, 4 and 8 threads; a control program that increments one variable
+from every thread of a parallel region shows that a race is reported.
 """
 
 from __future__ import annotations
@@ -92,3 +98,59 @@ def test_oracle_clean_under_sanitizers(builds):
         assert "runtime error" not in r.stderr, r.stderr[-4000:]
         assert "Sanitizer" not in r.stderr, r.stderr[-4000:]
         assert r.stdout == ref.stdout, (exe.name, threads, pad)
+
+
+LLVM_BIN = "/opt/rocm/llvm/bin/clang"
+LLVM_LIB = "/opt/rocm/llvm/lib"
+ARCHER = os.path.join(LLVM_LIB, "libarcher.so")
+needs_archer = pytest.mark.skipif(
+    not (os.path.exists(LLVM_BIN) and os.path.exists(ARCHER)),
+    reason="LLVM clang with the Archer OpenMP tool not found")
+TSAN = ["-O1", "-g", "-fsanitize=thread", "-fopenmp", "-Wl,-rpath," + LLVM_LIB]
+
+
+def _clang(out, srcs):
+    cmd = [LLVM_BIN, "-std=c11", "-fno-fast-math", "-ffp-contract=off", *TSAN, "-o", str(out),
+           *srcs, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+
+
+def _run_tsan(exe, *args):
+    env = dict(os.environ, OMP_TOOL_LIBRARIES=ARCHER,
+               TSAN_OPTIONS="ignore_noninstrumented_modules=1")
+    env.pop("ARCHER_OPTIONS", None)
+    return subprocess.run([str(exe), *map(str, args)], capture_output=True, text=True,
+                          timeout=300, env=env)
+
+
+@needs_archer
+def test_thread_sanitizer_catches_a_race(tmp_path):
+    src = tmp_path / "race.c"
+    src.write_text("#include <stdio.h>\n"
+                   "int main(void) {\n"
+                   "    int x = 0;\n"
+                   "#pragma omp parallel num_threads(4)\n"
+                   "    x += 1;   /* every thread, unsynchronised */\n"
+                   "    printf(\"%d\\n\", x > 0);\n"
+                   "    return 0;\n"
+                   "}\n")
+    exe = tmp_path / "race"
+    _clang(exe, [str(src)])
+    r = _run_tsan(exe)
+    assert r.returncode != 0
+    assert "ThreadSanitizer: data race" in r.stderr, r.stderr
+
+
+@needs_archer
+def test_oracle_clean_under_thread_sanitizer(builds, tmp_path):
+    _, plain, _ = builds
+    ref = _run(plain, 2, -7)
+    assert ref.returncode == 0, ref.stderr
+    exe = tmp_path / "tsan"
+    _clang(exe, [DRIVER, *ORACLE_SRCS])
+    for threads in (2, 4, 8):
+        r = _run_tsan(exe, threads, -7)
+        assert r.returncode == 0, (threads, r.stderr[-4000:])
+        assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+        assert r.stdout == ref.stdout, threads
