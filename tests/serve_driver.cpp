@@ -1,7 +1,8 @@
 // Drives the repositioning server from several client threads: test
 // infrastructure for the sanitizer builds of the library's host runtime (the
 // server's scheduler thread, its queues and tables, the launch sets and the
-// error and timing state).  Every C-ABI call takes host buffers only.
+// error and timing state).  The server's calls take host buffers; the plain
+// solves of part 4 take device buffers.
 //
 //   1. A server with four slots and a budget that holds about two of the
 //      eight instances' tables: four client threads each own two instances and
@@ -13,6 +14,10 @@
 //      request's result depends only on its instance's missions, its warm
 //      start and its parameters).
 //   3. A third server is closed with requests still waiting and running.
+//   4. The same chains through fs_tabu_solve, fs_tabu_solve_noalloc and
+//      fs_tabu_solve_batch (tables from fs_build_cost_table, each request
+//      warm-started from the served result before it) must give the served
+//      results.
 //
 // Prints one line and exits 0 when every result matches, 1 otherwise.
 #include <atomic>
@@ -22,6 +27,8 @@
 #include <cstring>
 #include <thread>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "fleetstage.h"
 
@@ -184,6 +191,143 @@ bool register_all(fs_server *sv, const std::vector<Spec> &specs, std::vector<int
     return true;
 }
 
+bool same(const Result &a, const Result &b)
+{
+    return a.open == b.open && a.score.coverage == b.score.coverage &&
+           a.score.distance == b.score.distance && a.score.best_iter == b.score.best_iter;
+}
+
+bool hip_ok(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return true;
+    std::fprintf(stderr, "%s: %s\n", what, hipGetErrorString(e));
+    return false;
+}
+
+template <typename T>
+T *dev_alloc(size_t n, std::vector<void *> &owned)
+{
+    void *p = nullptr;
+    if (!hip_ok(hipMalloc(&p, sizeof(T) * (n ? n : 1)), "hipMalloc")) return nullptr;
+    owned.push_back(p);
+    return (T *)p;
+}
+
+// The served chains again through fs_tabu_solve, fs_tabu_solve_noalloc and
+// one fs_tabu_solve_batch per request round over every instance, each warm
+// started from the previous request's result like the server.  Counts the
+// results that differ from the served ones; -1 on a failed call.
+int plain_chains(const std::vector<Spec> &specs, const std::vector<std::vector<Result>> &served)
+{
+    std::vector<void *> owned;
+    struct Dev {
+        std::vector<double> missions;
+        double *bases = nullptr, *pd = nullptr;
+        int32_t *C = nullptr, *init = nullptr, *best = nullptr, *best_na = nullptr,
+                *best_b = nullptr;
+    };
+    std::vector<Dev> dv(specs.size());
+    for (size_t i = 0; i < specs.size(); ++i) {
+        const Spec &s = specs[i];
+        Dev &d = dv[i];
+        d.missions = s.missions;
+        d.bases = dev_alloc<double>(2 * (size_t)s.B, owned);
+        d.pd = dev_alloc<double>(4 * (size_t)s.M, owned);
+        d.C = dev_alloc<int32_t>((size_t)s.B * s.M, owned);
+        d.init = dev_alloc<int32_t>(s.K, owned);
+        d.best = dev_alloc<int32_t>(s.K, owned);
+        d.best_na = dev_alloc<int32_t>(s.K, owned);
+        d.best_b = dev_alloc<int32_t>(s.K, owned);
+        if (!d.bases || !d.pd || !d.C || !d.init || !d.best || !d.best_na || !d.best_b) return -1;
+        if (!hip_ok(hipMemcpy(d.bases, s.bases.data(), 16 * (size_t)s.B, hipMemcpyHostToDevice),
+                    "copy bases"))
+            return -1;
+    }
+    int differ = 0;
+    for (int r = 0; r < kChain; ++r) {
+        const fs_params p = params_of(r);
+        std::vector<fs_instance> batch(specs.size());
+        for (size_t i = 0; i < specs.size(); ++i) {
+            const Spec &s = specs[i];
+            Dev &d = dv[i];
+            const Request q = make_request(s, (int)i, r);
+            for (size_t k = 0; k < q.ids.size(); ++k)
+                std::memcpy(&d.missions[4 * (size_t)q.ids[k]], &q.pd[4 * k], 32);
+            if (!hip_ok(hipMemcpy(d.pd, d.missions.data(), 32 * (size_t)s.M,
+                                  hipMemcpyHostToDevice),
+                        "copy missions") ||
+                !check(fs_build_cost_table(d.bases, s.B, d.pd, s.M, 0, 3, d.C, s.M, nullptr,
+                                           nullptr),
+                       "cost table"))
+                return -1;
+            const int32_t *init = nullptr;
+            if (r > 0) {   // warm start: the previous request's served result
+                if (!hip_ok(hipMemcpy(d.init, served[i][r - 1].open.data(), 4 * (size_t)s.K,
+                                      hipMemcpyHostToDevice),
+                            "copy init"))
+                    return -1;
+                init = d.init;
+            }
+            fs_params pr = p;   // the server takes the range from the instance
+            pr.range_m = s.R;
+            Result a, b;
+            if (!check(fs_tabu_solve(d.C, s.M, s.B, s.M, s.K, &pr, init, d.best, &a.score,
+                                     nullptr, nullptr, nullptr),
+                       "solve") ||
+                !check(fs_tabu_solve_noalloc(d.C, s.M, s.B, s.M, s.K, &pr, init, d.best_na,
+                                             &b.score, nullptr, nullptr, nullptr),
+                       "solve without allocation"))
+                return -1;
+            a.open.resize(s.K);
+            b.open.resize(s.K);
+            if (!hip_ok(hipMemcpy(a.open.data(), d.best, 4 * (size_t)s.K, hipMemcpyDeviceToHost),
+                        "copy best") ||
+                !hip_ok(hipMemcpy(b.open.data(), d.best_na, 4 * (size_t)s.K,
+                                  hipMemcpyDeviceToHost),
+                        "copy best"))
+                return -1;
+            if (!same(a, served[i][r])) {
+                std::fprintf(stderr, "instance %zu request %d: fs_tabu_solve differs\n", i, r);
+                ++differ;
+            }
+            if (!same(b, served[i][r])) {
+                std::fprintf(stderr, "instance %zu request %d: noalloc differs\n", i, r);
+                ++differ;
+            }
+            fs_instance &in = batch[i];
+            in = fs_instance{};
+            in.C = d.C;
+            in.ldc = s.M;
+            in.B = s.B;
+            in.M = s.M;
+            in.K = s.K;
+            in.range_m = s.R;
+            in.init_open = init;
+            in.best_open_out = d.best_b;
+        }
+        std::vector<fs_score> scores(specs.size());
+        if (!check(fs_tabu_solve_batch(batch.data(), (int32_t)batch.size(), &p, scores.data(),
+                                       nullptr),
+                   "batch"))
+            return -1;
+        for (size_t i = 0; i < specs.size(); ++i) {
+            Result c;
+            c.score = scores[i];
+            c.open.resize(specs[i].K);
+            if (!hip_ok(hipMemcpy(c.open.data(), dv[i].best_b, 4 * (size_t)specs[i].K,
+                                  hipMemcpyDeviceToHost),
+                        "copy best"))
+                return -1;
+            if (!same(c, served[i][r])) {
+                std::fprintf(stderr, "instance %zu request %d: batch differs\n", i, r);
+                ++differ;
+            }
+        }
+    }
+    for (void *q : owned) (void)hipFree(q);
+    return differ;
+}
+
 }  // namespace
 
 int main()
@@ -238,14 +382,11 @@ int main()
     if (!check(fs_serve_close(sv), "close")) return 1;
     int mismatches = 0;
     for (int i = 0; i < kInstances; ++i)
-        for (int r = 0; r < kChain; ++r) {
-            const Result &a = mixed[i][r], &b = alone[i][r];
-            if (a.open != b.open || a.score.coverage != b.score.coverage ||
-                a.score.distance != b.score.distance || a.score.best_iter != b.score.best_iter) {
+        for (int r = 0; r < kChain; ++r)
+            if (!same(mixed[i][r], alone[i][r])) {
                 std::fprintf(stderr, "instance %d request %d differs\n", i, r);
                 ++mismatches;
             }
-        }
 
     // 3. close with requests waiting and running
     if (!open_server(tight, 2, &sv)) return 1;
@@ -260,6 +401,11 @@ int main()
             return 1;
     }
     if (!check(fs_serve_close(sv), "close in flight")) return 1;
+
+    // 4. the same chains through the plain, allocation-free and batch solves
+    const int plain = plain_chains(specs, mixed);
+    if (plain < 0) return 1;
+    mismatches += plain;
 
     std::printf("serve driver: %d requests, %lld evictions, %lld rebuilds, %lld counter reads, "
                 "%d mismatches\n",
