@@ -14,10 +14,10 @@
 //      request's result depends only on its instance's missions, its warm
 //      start and its parameters).
 //   3. A third server is closed with requests still waiting and running.
-//   4. The same chains through fs_tabu_solve, fs_tabu_solve_noalloc and
-//      fs_tabu_solve_batch (tables from fs_build_cost_table, each request
-//      warm-started from the served result before it) must give the served
-//      results.
+//   4. The same chains through fs_tabu_solve, fs_tabu_solve_noalloc,
+//      fs_tabu_solve_batch and fs_fleet_solve with a fleet that every base can
+//      hold (tables from fs_build_cost_table, each request warm-started from
+//      the served result before it) must give the served results.
 //
 // Prints one line and exits 0 when every result matches, 1 otherwise.
 #include <atomic>
@@ -213,8 +213,9 @@ T *dev_alloc(size_t n, std::vector<void *> &owned)
     return (T *)p;
 }
 
-// The served chains again through fs_tabu_solve, fs_tabu_solve_noalloc and
-// one fs_tabu_solve_batch per request round over every instance, each warm
+// The served chains again through fs_tabu_solve, fs_tabu_solve_noalloc,
+// fs_fleet_solve (no heliport, no rotary-only mission) and one
+// fs_tabu_solve_batch per request round over every instance, each warm
 // started from the previous request's result like the server.  Counts the
 // results that differ from the served ones; -1 on a failed call.
 int plain_chains(const std::vector<Spec> &specs, const std::vector<std::vector<Result>> &served)
@@ -225,6 +226,7 @@ int plain_chains(const std::vector<Spec> &specs, const std::vector<std::vector<R
         double *bases = nullptr, *pd = nullptr;
         int32_t *C = nullptr, *init = nullptr, *best = nullptr, *best_na = nullptr,
                 *best_b = nullptr;
+        int32_t *heli = nullptr, *init_rot = nullptr, *best_f = nullptr, *rot_f = nullptr;
     };
     std::vector<Dev> dv(specs.size());
     for (size_t i = 0; i < specs.size(); ++i) {
@@ -238,7 +240,20 @@ int plain_chains(const std::vector<Spec> &specs, const std::vector<std::vector<R
         d.best = dev_alloc<int32_t>(s.K, owned);
         d.best_na = dev_alloc<int32_t>(s.K, owned);
         d.best_b = dev_alloc<int32_t>(s.K, owned);
-        if (!d.bases || !d.pd || !d.C || !d.init || !d.best || !d.best_na || !d.best_b) return -1;
+        d.heli = dev_alloc<int32_t>(s.B, owned);
+        d.init_rot = dev_alloc<int32_t>(s.K, owned);
+        d.best_f = dev_alloc<int32_t>(s.K, owned);
+        d.rot_f = dev_alloc<int32_t>(s.K, owned);
+        if (!d.bases || !d.pd || !d.C || !d.init || !d.best || !d.best_na || !d.best_b ||
+            !d.heli || !d.init_rot || !d.best_f || !d.rot_f)
+            return -1;
+        // a fleet with no heliport: the first K/2 slots rotary-wing
+        std::vector<int32_t> rot((size_t)s.K);
+        for (int32_t k = 0; k < s.K; ++k) rot[k] = k < s.K / 2;
+        if (!hip_ok(hipMemset(d.heli, 0, 4 * (size_t)s.B), "clear heliports") ||
+            !hip_ok(hipMemcpy(d.init_rot, rot.data(), 4 * (size_t)s.K, hipMemcpyHostToDevice),
+                    "copy types"))
+            return -1;
         if (!hip_ok(hipMemcpy(d.bases, s.bases.data(), 16 * (size_t)s.B, hipMemcpyHostToDevice),
                     "copy bases"))
             return -1;
@@ -292,6 +307,28 @@ int plain_chains(const std::vector<Spec> &specs, const std::vector<std::vector<R
             }
             if (!same(b, served[i][r])) {
                 std::fprintf(stderr, "instance %zu request %d: noalloc differs\n", i, r);
+                ++differ;
+            }
+            // with every base an aerodrome and no rotary-only mission, the
+            // typed search makes the untyped search's moves
+            fs_fleet fl{};
+            fl.rotary = s.K / 2;
+            fl.fixed = s.K - s.K / 2;
+            fl.heliport = d.heli;
+            fl.rotary_only = nullptr;
+            Result f;
+            if (!check(fs_fleet_solve(d.C, s.M, s.B, s.M, &fl, &pr, init,
+                                      init ? d.init_rot : nullptr, d.best_f, d.rot_f, &f.score,
+                                      nullptr, nullptr, nullptr),
+                       "fleet solve"))
+                return -1;
+            f.open.resize(s.K);
+            if (!hip_ok(hipMemcpy(f.open.data(), d.best_f, 4 * (size_t)s.K,
+                                  hipMemcpyDeviceToHost),
+                        "copy best"))
+                return -1;
+            if (!same(f, served[i][r])) {
+                std::fprintf(stderr, "instance %zu request %d: fleet solve differs\n", i, r);
                 ++differ;
             }
             fs_instance &in = batch[i];
