@@ -58,6 +58,16 @@ def test_two_legs_pitch_and_many_hospitals():
         assert np.array_equal(Cfi.view(np.int64), Cfd.view(np.int64))
 
 
+@pytest.mark.parametrize("H", [10_240, 10_241])
+def test_workgroup_size_boundary(H):
+    # the largest hospital count whose legs fit two workgroups in a CU's LDS
+    # (768-thread workgroups) and the smallest that does not (1,024 threads)
+    inst = synth.make_instance(seed=63, B=23, H=H, M=1501)
+    (Cd, Cfd), (Ci, Cfi) = both(inst, ldc=1504)
+    assert np.array_equal(Ci, Cd)
+    assert np.array_equal(Cfi.view(np.int64), Cfd.view(np.int64))
+
+
 def test_bad_ids_and_too_many_hospitals_are_errors():
     inst = synth.make_instance(seed=62, B=5, H=30, M=40)
     ph = inst.mission_ph.copy()
