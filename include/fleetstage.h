@@ -264,7 +264,7 @@ fs_status fs_fleet_move_scores(const int32_t *C, int64_t ldc, int32_t B, int32_t
  * exactly as fs_tabu_solve otherwise (tabu list, aspiration, order (cov desc,
  * dist asc, out-base asc, in-base asc), N iterations).  init_open / init_rotary
  * (device, K) give the initial placement and its vehicle types, or init_open =
- * NULL for the typed base ranking of Algorithm 1 (lines 13-21): bases in
+ * NULL for the typed base ranking (Algorithm 1 with its helipad quota): bases in
  * (row sum, id) order, a heliport taken only while fewer than K_r are,
  * rotary-wing vehicles on the chosen heliports and then on the best-ranked
  * chosen aerodromes, fixed-wing on the rest.  A vehicle keeps its type when it

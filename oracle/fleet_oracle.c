@@ -1,8 +1,8 @@
 /*
  * fleet_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
  *
- * The heterogeneous-fleet model of the paper (Section 3, Eq. 2-10; Algorithm 1
- * lines 13-29), as a plain CPU reference for the typed HIP path.  Same status
+ * The heterogeneous-fleet model of the paper (Section 3, Eq. 2-10; the typed
+ * part of Algorithm 1), as a plain CPU reference for the typed HIP path.  Same status
  * and rules as fleetstage_oracle.c: loaded only by the tests, the smoke check
  * and the benchmark's CPU baseline; shares no code with the HIP path.
  *
@@ -22,12 +22,11 @@
  *     an unoccupied base j that can hold it (a fixed-wing vehicle only to an
  *     aerodrome): the base-swap neighbourhood of the homogeneous case with the
  *     type constraint.  Move order, tabu rule and aspiration are unchanged.
- *   - Base ranking (Algorithm 1, lines 13-21): bases in ascending (row sum,
- *     id) order; once K_r heliports are chosen no further heliport is taken
- *     (lines 14-16); rotary-wing vehicles go to the chosen heliports first
- *     (line 20), then the remaining rotary-wing vehicles to the chosen
- *     aerodromes in rank order, then the fixed-wing vehicles to the rest
- *     (line 21).
+ *   - Base ranking (Algorithm 1 with its helipad quota): bases in ascending
+ *     (row sum, id) order; once K_r heliports are chosen no further heliport
+ *     is taken; rotary-wing vehicles go to the chosen heliports first, then
+ *     the remaining rotary-wing vehicles to the chosen aerodromes in rank
+ *     order, then the fixed-wing vehicles to the rest.
  * With no heliports, no rotary-only mission and every vehicle rotary-wing the
  * model is exactly the homogeneous one (a test pins this).
  */
@@ -133,7 +132,7 @@ void fso_fleet_move_scores(const int32_t *C, int64_t ldc, int32_t B, int32_t M,
     free(occ);
 }
 
-/* Base ranking with types (Algorithm 1, lines 13-21; reading in the header).
+/* Base ranking with types (Algorithm 1's helipad quota; reading in the header).
  * open_out: K base ids, rot_out: their vehicle types, in slot order (the
  * chosen heliports, then the chosen aerodromes, each group in rank order).
  * Returns 0, or -1 when the bases cannot hold the fleet (fewer than K_f

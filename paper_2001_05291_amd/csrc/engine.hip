@@ -334,7 +334,7 @@ __device__ int32_t block_exclusive(int32_t v, int32_t *s_cnt, int32_t *total)
     return r;
 }
 
-// Typed base ranking (heterogeneous fleet, Algorithm 1 lines 13-21): walking
+// Typed base ranking (heterogeneous fleet, Algorithm 1's helipad quota): walking
 // the bases in (row sum, id) order, a heliport is taken only while fewer than
 // K_r heliports are; the first K bases so taken are chosen.  Slots: the chosen
 // heliports first, then the chosen aerodromes, each in rank order; vehicles:

@@ -1,7 +1,8 @@
 // Heterogeneous-fleet entry points: fs_fleet_move_scores and fs_fleet_solve
 // (Section 3, Eq. 4-10: rotary-wing and fixed-wing vehicles, aerodromes and
-// heliports, rotary-only missions; the typed base ranking of Algorithm 1,
-// lines 13-21; the Tabu search of Section 4.3 over vehicle relocations).
+// heliports, rotary-only missions; the typed base ranking, the helipad-quota
+// part of Algorithm 1; the Tabu search of Section 4.3 over vehicle
+// relocations).
 // They drive the same engine as the homogeneous calls: a typed instance
 // differs only in its per-slot vehicle types, the base kinds carried beside
 // the lists and the per-mission kind carried in the nearest-slot word.

@@ -10,8 +10,9 @@
 duration).  ``traffic`` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per
 dispatch, summed over the counter instances of a dispatch) of one kernel into
 bytes per launch, each scaled by what the same counter reads for a plain copy
-kernel of known size, and records the hash of the kernel source it was taken
-with so that a stale figure is not reported for changed code.
+kernel of known size, and records the hash of the kernel code it was taken
+with (the source with its comments removed and its whitespace collapsed) so
+that a stale figure is not reported for changed code.
 """
 
 from __future__ import annotations
@@ -27,9 +28,36 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 SWEEP_SOURCE = os.path.join(PKG, "csrc", "engine.hip")
 
 
-def source_hash(path: str = SWEEP_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def strip_comments(src: str) -> str:
+    """C++ source without its // and /* */ comments (string and character
+    literals kept as they are), every run of whitespace made one space."""
+    out = []
+    i, n = 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def code_hash(path: str = SWEEP_SOURCE) -> str:
+    """Hash of the kernel code: a change to a comment keeps it."""
+    with open(path, encoding="utf-8") as f:
+        return hashlib.sha256(strip_comments(f.read()).encode()).hexdigest()[:16]
 
 
 def short_name(name: str) -> str:
@@ -125,7 +153,7 @@ def write_traffic(fetch_db: str, write_db: str, kernel_re: str, copy_re: str, co
              f"(traffic / algorithmic = {total / algorithmic:.3f})", "",
              f"workload: {workload}",
              f"traffic_bytes_per_launch: {total:.0f}",
-             f"source_sha256: {source_hash()}"]
+             f"code_sha256: {code_hash()}"]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return total
@@ -152,7 +180,7 @@ def write_valu(db: str, kernel_re: str, out: str, commands, workload: str):
              f"- lane-operations per launch (x 64 lanes): {64 * v:.0f}", "",
              f"workload: {workload}",
              f"valu_lane_ops_per_launch: {64 * v:.0f}",
-             f"source_sha256: {source_hash()}"]
+             f"code_sha256: {code_hash()}"]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return 64 * v
@@ -167,7 +195,7 @@ def read_valu(path: str, workload: str):
     except OSError:
         return None
     kv = dict(re.findall(r"^(\w+): (.+)$", text, re.M))
-    if kv.get("workload") != workload or kv.get("source_sha256") != source_hash():
+    if kv.get("workload") != workload or kv.get("code_sha256") != code_hash():
         return None
     return float(kv["valu_lane_ops_per_launch"])
 
@@ -213,7 +241,7 @@ def read_traffic(path: str, workload: str):
     except OSError:
         return None
     kv = dict(re.findall(r"^(\w+): (.+)$", text, re.M))
-    if kv.get("workload") != workload or kv.get("source_sha256") != source_hash():
+    if kv.get("workload") != workload or kv.get("code_sha256") != code_hash():
         return None
     return float(kv["traffic_bytes_per_launch"])
 
