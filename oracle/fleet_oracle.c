@@ -6,7 +6,7 @@
  * and rules as fleetstage_oracle.c: loaded only by the tests, the smoke check
  * and the benchmark's CPU baseline; shares no code with the HIP path.
  *
- * Readings (also listed in the design notes):
+ * Readings of the paper followed here:
  *   - Bases are aerodromes, which can hold either vehicle type, or heliports,
  *     which hold rotary-wing vehicles only; every base holds at most one
  *     vehicle (Eq. 6, 7).  heliport[b] = 1 marks a heliport.

@@ -7,7 +7,7 @@
  * fleetstage_oracle.c: loaded only by the tests, the smoke check and the
  * benchmark's CPU baseline; shares no code with the HIP path.
  *
- * Readings (also listed in the design notes):
+ * Readings of the paper followed here:
  *   - With moves read as base swaps, the two random mission orders of the
  *     paper become one random order over the swap moves.  Each pass draws a
  *     fresh order: move (i, j) (base i leaves, base j enters) has priority
