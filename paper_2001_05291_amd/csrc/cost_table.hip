@@ -58,31 +58,54 @@ __global__ __launch_bounds__(kBlock) void k_mission_prep(const double *__restric
     mp.pd[m] = haversine(phi_p, psi_p, cos_p, phi_d, psi_d, cos_d, two_r);
 }
 
+// Angles and latitude cosine of the kBasesPerBlock bases from b0 on, computed
+// by the block's first threads into LDS for the whole block: the values every
+// thread would compute itself, at one cosine per base instead of one per
+// (base, mission).  Called by every thread of the block.
+__device__ __forceinline__ void stage_bases(const double *__restrict__ bases, int32_t B,
+                                            int32_t b0, double (*s_base)[3])
+{
+    __syncthreads();   // the previous group's reads are done
+    const int32_t t = threadIdx.x;
+    if (t < kBasesPerBlock && b0 + t < B) {
+        const double phi = bases[2 * (int64_t)(b0 + t)] * kDeg2Rad;
+        s_base[t][0] = phi;
+        s_base[t][1] = bases[2 * (int64_t)(b0 + t) + 1] * kDeg2Rad;
+        s_base[t][2] = cos(phi);
+    }
+    __syncthreads();
+}
+
 // grid: x = mission blocks of kBlock, y = base groups of kBasesPerBlock.
 __global__ __launch_bounds__(kBlock) void k_cost_table(const double *__restrict__ bases, int32_t B,
                                                        int32_t M, double two_r, int32_t legs,
                                                        MissionPrep mp, int32_t *__restrict__ C,
                                                        double *__restrict__ Cf, int64_t ldc)
 {
-    int32_t m = blockIdx.x * kBlock + threadIdx.x;
-    if (m >= M) return;
-    double phi_p = mp.phi_p[m], psi_p = mp.psi_p[m], cos_p = mp.cos_p[m];
-    double phi_d = mp.phi_d[m], psi_d = mp.psi_d[m], cos_d = mp.cos_d[m];
-    double pd = mp.pd[m];
-    for (int32_t b0 = blockIdx.y * kBasesPerBlock; b0 < B; b0 += gridDim.y * kBasesPerBlock)
+    __shared__ double s_base[kBasesPerBlock][3];
+    const int32_t m = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = m < M;   // no early exit: every thread takes the barriers
+    double phi_p = 0, psi_p = 0, cos_p = 0, phi_d = 0, psi_d = 0, cos_d = 0, pd = 0;
+    if (valid) {
+        phi_p = mp.phi_p[m], psi_p = mp.psi_p[m], cos_p = mp.cos_p[m];
+        phi_d = mp.phi_d[m], psi_d = mp.psi_d[m], cos_d = mp.cos_d[m];
+        pd = mp.pd[m];
+    }
+    for (int32_t b0 = blockIdx.y * kBasesPerBlock; b0 < B; b0 += gridDim.y * kBasesPerBlock) {
+        stage_bases(bases, B, b0, s_base);
+        if (!valid) continue;
 #pragma unroll
-    for (int q = 0; q < kBasesPerBlock; ++q) {
-        int32_t b = b0 + q;
-        if (b >= B) break;
-        double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
-        double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
-        double cos_b = cos(phi_b);
-        double bp = haversine(phi_b, psi_b, cos_b, phi_p, psi_p, cos_p, two_r);
-        double db = haversine(phi_d, psi_d, cos_d, phi_b, psi_b, cos_b, two_r);
-        double v = (legs == 3) ? (bp + pd) + db : bp + db;
-        int64_t at = (int64_t)b * ldc + m;
-        C[at] = (int32_t)rint(v);
-        if (Cf) Cf[at] = v;
+        for (int q = 0; q < kBasesPerBlock; ++q) {
+            const int32_t b = b0 + q;
+            if (b >= B) break;
+            const double phi_b = s_base[q][0], psi_b = s_base[q][1], cos_b = s_base[q][2];
+            const double bp = haversine(phi_b, psi_b, cos_b, phi_p, psi_p, cos_p, two_r);
+            const double db = haversine(phi_d, psi_d, cos_d, phi_b, psi_b, cos_b, two_r);
+            const double v = (legs == 3) ? (bp + pd) + db : bp + db;
+            const int64_t at = (int64_t)b * ldc + m;
+            C[at] = (int32_t)rint(v);
+            if (Cf) Cf[at] = v;
+        }
     }
 }
 
@@ -95,27 +118,31 @@ __global__ __launch_bounds__(kBlock) void k_cost_columns(const double *__restric
                                                          int32_t M, double two_r, int32_t legs,
                                                          int32_t *__restrict__ C, int64_t ldc)
 {
+    __shared__ double s_base[kBasesPerBlock][3];
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int32_t m = ids[i];
-    if (m < 0 || m >= M) return;
-    const double *q = mpd + 4 * (int64_t)i;
-    const double phi_p = q[0] * kDeg2Rad, psi_p = q[1] * kDeg2Rad;
-    const double phi_d = q[2] * kDeg2Rad, psi_d = q[3] * kDeg2Rad;
-    const double cos_p = cos(phi_p), cos_d = cos(phi_d);
-    const double pd = haversine(phi_p, psi_p, cos_p, phi_d, psi_d, cos_d, two_r);
-    for (int32_t b0 = blockIdx.y * kBasesPerBlock; b0 < B; b0 += gridDim.y * kBasesPerBlock)
+    const int32_t m = i < n ? ids[i] : -1;
+    const bool valid = m >= 0 && m < M;   // no early exit: every thread takes the barriers
+    double phi_p = 0, psi_p = 0, cos_p = 0, phi_d = 0, psi_d = 0, cos_d = 0, pd = 0;
+    if (valid) {
+        const double *q = mpd + 4 * (int64_t)i;
+        phi_p = q[0] * kDeg2Rad, psi_p = q[1] * kDeg2Rad;
+        phi_d = q[2] * kDeg2Rad, psi_d = q[3] * kDeg2Rad;
+        cos_p = cos(phi_p), cos_d = cos(phi_d);
+        pd = haversine(phi_p, psi_p, cos_p, phi_d, psi_d, cos_d, two_r);
+    }
+    for (int32_t b0 = blockIdx.y * kBasesPerBlock; b0 < B; b0 += gridDim.y * kBasesPerBlock) {
+        stage_bases(bases, B, b0, s_base);
+        if (!valid) continue;
 #pragma unroll
-    for (int q2 = 0; q2 < kBasesPerBlock; ++q2) {
-        const int32_t b = b0 + q2;
-        if (b >= B) break;
-        const double phi_b = bases[2 * (int64_t)b] * kDeg2Rad;
-        const double psi_b = bases[2 * (int64_t)b + 1] * kDeg2Rad;
-        const double cos_b = cos(phi_b);
-        const double bp = haversine(phi_b, psi_b, cos_b, phi_p, psi_p, cos_p, two_r);
-        const double db = haversine(phi_d, psi_d, cos_d, phi_b, psi_b, cos_b, two_r);
-        const double v = (legs == 3) ? (bp + pd) + db : bp + db;
-        C[(int64_t)b * ldc + m] = (int32_t)rint(v);
+        for (int q2 = 0; q2 < kBasesPerBlock; ++q2) {
+            const int32_t b = b0 + q2;
+            if (b >= B) break;
+            const double phi_b = s_base[q2][0], psi_b = s_base[q2][1], cos_b = s_base[q2][2];
+            const double bp = haversine(phi_b, psi_b, cos_b, phi_p, psi_p, cos_p, two_r);
+            const double db = haversine(phi_d, psi_d, cos_d, phi_b, psi_b, cos_b, two_r);
+            const double v = (legs == 3) ? (bp + pd) + db : bp + db;
+            C[(int64_t)b * ldc + m] = (int32_t)rint(v);
+        }
     }
 }
 
